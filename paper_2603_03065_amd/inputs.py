@@ -1,0 +1,72 @@
+"""Seeded synthetic inputs, shared by the GPU path's tests/benchmarks and the oracle's.
+
+This module holds no arithmetic of the method: it only draws uniform Goldilocks
+field elements and workload shapes from a counter-based SplitMix64 stream, so the
+same trace can be rebuilt anywhere from (seed, trace_id, col, row).
+
+Element (seed, trace_id, col, row) = canon(SplitMix64(seed, (trace_id << 40) | (col << 24) | row)),
+where SplitMix64(seed, i) is output i of the generator started at `seed` (the state
+advances by 0x9E3779B97F4A7C15 before each output, then the published finaliser
+mixes it) and canon(z) = z - p if z >= p else z.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+P = 0xFFFFFFFF00000001
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, idx) -> np.ndarray:
+    """Vectorised SplitMix64 output idx (0-based) for a stream started at seed."""
+    i = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (i + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def canon(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    return np.where(z >= np.uint64(P), z - np.uint64(P), z)
+
+
+def trace(seed: int, trace_id: int, n_cols: int, log_rows: int, col0: int = 0) -> np.ndarray:
+    """Column-major trace [n_cols][2^log_rows] of uniform field elements."""
+    assert log_rows <= 24 and col0 + n_cols <= (1 << 16)
+    rows = np.arange(1 << log_rows, dtype=np.uint64)
+    out = np.empty((n_cols, 1 << log_rows), dtype=np.uint64)
+    base = np.uint64(trace_id) << np.uint64(40)
+    for c in range(n_cols):
+        idx = base | (np.uint64(col0 + c) << np.uint64(24)) | rows
+        out[c] = canon(splitmix64(seed, idx))
+    return out
+
+
+def states(seed: int, count: int) -> np.ndarray:
+    """count random Poseidon states [count][12], uniform in [0, p)."""
+    return canon(splitmix64(seed, np.arange(count * 12, dtype=np.uint64))).reshape(count, 12)
+
+
+# ---- workload shapes ---------------------------------------------------------
+
+BATCH_SHAPE_STREAM = 0x5634_0004
+
+
+def batch_shapes(n_traces: int = 64, stream: int = BATCH_SHAPE_STREAM):
+    """(log_rows, n_cols) per trace of the batched workload: log_rows uniform in
+    10..18 and columns uniform in 20..135, drawn from a SplitMix64 stream."""
+    out = []
+    for t in range(n_traces):
+        lr = 10 + int(splitmix64(stream, 2 * t)) % 9
+        nc = 20 + int(splitmix64(stream, 2 * t + 1)) % 116
+        out.append((lr, nc))
+    return out
+
+
+def uniform01(stream: int, i) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the top 53 bits of SplitMix64(stream, i)."""
+    return (splitmix64(stream, i) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
