@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Commit throughput on one MI355X: coset LDE + Poseidon leaf hashing + Merkle cap.
+
+A step is one whole commit (v3db_commit_batch with one job: three LDE passes,
+the leaf sponge over every extended row, every Merkle level up to the cap) of a
+synthetic trace already resident in HBM. Default workload: 80 columns x 2^18
+rows of uniform Goldilocks elements, blowup 8 (2^21 extended rows), rate-8
+sponge rows, cap height 4, natural layout.
+
+Prints one JSON line: LDE elements committed per second (value), per-step
+p50/p99 latency, the dominant kernel against its roofline (timed live with HIP
+events on the library's stream), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LDE+Poseidon-Merkle committed field elems/s at 1 GPU; p50/p99 commit latency"
+
+WORKLOADS = {
+    # name: (description, n_cols, log_rows, log_blowup, cap_height, layout, data seed)
+    "commit-80x2^18": ("80 cols x 2^18 rows, blowup 8 -> 2^21 rows, sponge rows, cap height 4, natural layout",
+                       80, 18, 3, 4, 0, 2),
+    "commit-135x2^20": ("135 cols x 2^20 rows, blowup 8 -> 2^23 rows, sponge rows, cap height 4, bit-reversed layout",
+                        135, 20, 3, 4, 1, 3),
+    "commit-8x2^12": ("8 cols x 2^12 rows, blowup 8 -> 2^15 rows, one permutation per row, cap height 0",
+                      8, 12, 3, 0, 0, 1),
+}
+DEFAULT_WORKLOAD = "commit-80x2^18"
+
+# Peaks of one MI355X (gfx950): 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU
+# issue (v_mad_u64_u32 and v_mul_hi_u32 are full rate on this chip), 8 TB/s HBM3E.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic work (the cost model is derived in the design doc):
+#   one Poseidon permutation = 472 field multiplications x 10 + 4320 small-constant
+#   multiply-adds x 2 + 360 constant additions x 3 + 360 matrix-row folds x 6
+#   = 16,600 32-bit integer operations;
+#   one LDE element = 9 bytes of HBM traffic (1/8 element read, 1 element written).
+OPS_PER_PERMUTATION = 472 * 10 + 4320 * 2 + 360 * 3 + 360 * 6
+LDE_BYTES_PER_ELEMENT = 9
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
+                    help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
+    return ap.parse_args()
+
+
+def cpu_baseline(n_cols, log_blowup, cap_height, layout, log_rows):
+    import oracle
+    from paper_2603_03065_amd import inputs
+    tr = inputs.trace(99, 0, n_cols, log_rows)
+    threads = oracle.set_threads(0)
+    pos = oracle.Poseidon(260303065)
+    t0 = time.perf_counter()
+    pos.commit(tr, log_blowup, 7, layout, min(cap_height, log_rows + log_blowup))
+    dt = time.perf_counter() - t0
+    elems = n_cols << (log_rows + log_blowup)
+    return {
+        "value": elems / dt, "unit": "LDE field elems/s", "cores": threads, "kind": "oracle",
+        "seconds": dt,
+        "sample": f"one whole commit of {n_cols} cols x 2^{log_rows} rows (blowup {1 << log_blowup}, "
+                  f"cap height {cap_height}, same column count as the workload, fewer rows) on {threads} host threads",
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_03065_amd as v3db
+    from paper_2603_03065_amd import inputs
+
+    desc, C, L, b, h, layout, seed = WORKLOADS[args.workload]
+    n, N = 1 << L, 1 << (L + b)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    ctx = v3db.Context(0)
+    trace = v3db.to_device(inputs.trace(seed, 0, C, L), dev)
+    lde = torch.empty((C, N), dtype=torch.int64, device=dev)
+    tree = torch.empty((2 * N - (1 << h), 4), dtype=torch.int64, device=dev)
+    cap = torch.empty((1 << h, 4), dtype=torch.int64, device=dev)
+    job = v3db.Job(trace=trace, log_blowup=b, cap_height=h, shift=7, layout=layout, lde=lde, tree=tree, cap=cap)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        ctx.commit(job, stream)
+    torch.cuda.synchronize()
+
+    ctx.profile_enable(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for k in range(args.steps):
+        ctx.commit(job, stream)
+        marks[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = ctx.profile_read()
+    ctx.profile_enable(False)
+
+    step_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)])
+    elems = C * N
+    value = elems * args.steps / wall
+
+    leaf_ms, leaf_n = phases["leaf"]
+    lde_ms, lde_n = phases["lde"]
+    mk_ms, mk_n = phases["merkle"]
+    perms_leaf = N * math.ceil(C / 8)
+    leaf_avg_s = leaf_ms / max(leaf_n, 1) / 1e3
+    achieved = perms_leaf * OPS_PER_PERMUTATION / leaf_avg_s / 1e12
+    lde_avg_s = lde_ms / max(lde_n, 1) / 1e3
+    lde_gbs = elems * LDE_BYTES_PER_ELEMENT / lde_avg_s / 1e9
+    mk_avg_s = mk_ms / max(mk_n, 1) / 1e3
+    perms_merkle = N - (1 << h)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "LDE field elems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {desc}",
+            "n_cols": C, "log_rows": L, "log_blowup": b, "cap_height": h,
+            "layout": "bitrev" if layout else "natural", "shift": 7,
+            "lde_elements_per_step": elems, "trace_elements_per_step": C * n,
+            "poseidon_permutations_per_step": perms_leaf + perms_merkle,
+        },
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "min": float(step_ms.min()), "max": float(step_ms.max())},
+        "trace_elements_per_s": C * n * args.steps / wall,
+        "roofline": {
+            "kernel": "k_leaf_hash (rate-8 Poseidon sponge over every extended row)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s (32-bit integer VALU lane-ops)",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None,
+            "ops_per_launch": perms_leaf * OPS_PER_PERMUTATION,
+            "avg_launch_ms": leaf_avg_s * 1e3,
+        },
+        "phases": {
+            "lde": {"avg_ms": lde_avg_s * 1e3, "bound": "hbm", "achieved_GBps": lde_gbs, "peak_GBps": HBM_PEAK_GBS,
+                    "frac": lde_gbs / HBM_PEAK_GBS, "algorithmic_bytes": elems * LDE_BYTES_PER_ELEMENT},
+            "leaf": {"avg_ms": leaf_avg_s * 1e3, "permutations": perms_leaf,
+                     "permutations_per_s": perms_leaf / leaf_avg_s},
+            "merkle": {"avg_ms": mk_avg_s * 1e3, "permutations": perms_merkle,
+                       "permutations_per_s": perms_merkle / mk_avg_s if mk_avg_s else None},
+        },
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(C, b, h, layout, min(args.cpu_sample_log_rows, L))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * v3db: trace commitment on AMD Instinct MI355X (gfx950).
+ *
+ * The commitment phase of proof generation in V3DB (arXiv 2603.03065): trace
+ * columns are interpolated and extended onto a coset of a larger power-of-two
+ * domain (the "FFT-based polynomial operations over a power-of-two evaluation
+ * domain" of §2.1, paragraph "Gate counts and proving time (binning effect)"),
+ * each extended row is hashed with Poseidon, and the row digests are committed
+ * with a Merkle tree whose top levels form a cap (Hash = Poseidon and
+ * commitments = Merkle trees over a fixed-length canonical sequence of field
+ * elements, §4.3 "Snapshot Commitments"; authentication paths fold by the bits of
+ * the leaf index, §4.4 "Snapshot-Binding Circuit").
+ *
+ * The paper names these pieces but not their parameters (its prover runs the
+ * default configuration of its proof backend, §5 "Evaluation environment"). This
+ * library fixes them as follows:
+ *   field    Goldilocks, p = 2^64 - 2^32 + 1; roots w_{2^k} = 7^((p-1)/2^k)
+ *   LDE      c = iNTT_n(a) (a_i = P(w_n^i)); LDE[k] = P(shift * w_N^k), N = n << log_blowup
+ *   hash     width-12 Poseidon, S-box x^7, rounds 4 full + 22 partial + 4 full,
+ *            each round = add round constants (all lanes), S-box, multiply by a
+ *            12x12 circulant MDS matrix M[i][j] = a[(j - i) mod 12]
+ *   constants  SplitMix64 stream with the context's seed: accepted outputs z < p
+ *            fill the 360 round constants round-major; then a[j] = 1 + (z mod 255)
+ *            for the next 12 outputs, redrawn until every square submatrix of M
+ *            is nonsingular mod p
+ *   sponge   zero state; each chunk of up to 8 row elements (columns in order)
+ *            overwrites lanes 0..k-1, then permute; digest = lanes 0..3
+ *   node     Compress(L, R) = permute(L || R || 0,0,0,0) lanes 0..3
+ *   tree     leaves = digests of the stored rows; left child = even index
+ *
+ * Conventions for every call:
+ *   - All data pointers are device pointers unless stated otherwise. Field
+ *     elements are uint64 and must be canonical (< p); outputs are canonical.
+ *   - Matrices are column-major: column c of an R-row matrix is elements
+ *     [c*R, (c+1)*R). Digests are [count][4] row-major.
+ *   - The caller owns every buffer. Calls validate arguments on the host, enqueue
+ *     work on `stream` (a hipStream_t; NULL = the default stream) and return;
+ *     buffers must stay alive until the stream reaches that point.
+ *   - A context is used from one host thread at a time (the server API below is
+ *     the exception). Calls on one context that share its scratch must not
+ *     overlap on different streams; see v3db_commit_batch.
+ *   - Errors are returned as v3db_status; v3db_last_error() gives a message for
+ *     the last failing call on the calling thread. No exception crosses the ABI.
+ */
+#ifndef V3DB_H
+#define V3DB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct v3db_ctx v3db_ctx;
+typedef struct v3db_server v3db_server;
+typedef void *v3db_stream; /* a hipStream_t */
+
+typedef enum {
+  V3DB_OK = 0,
+  V3DB_ERR_INVALID_ARG = 1,   /* NULL pointer, zero columns, cap_height > log_leaves, shift 0 or >= p, ... */
+  V3DB_ERR_UNSUPPORTED = 2,   /* sizes beyond the build limits below */
+  V3DB_ERR_NONCANONICAL = 3,  /* an input element >= p (checked only when validation is on) */
+  V3DB_ERR_OUT_OF_MEMORY = 4, /* device allocation failed or the context's HBM budget would be exceeded */
+  V3DB_ERR_DEVICE = 5,        /* a HIP runtime error */
+  V3DB_ERR_BUSY = 6           /* server: request queue full */
+} v3db_status;
+
+typedef enum { V3DB_LAYOUT_NATURAL = 0, V3DB_LAYOUT_BITREV = 1 } v3db_layout;
+
+/* Build limits. */
+#define V3DB_MAX_LOG_ROWS 24    /* trace rows per column: 2^0 .. 2^24 */
+#define V3DB_MAX_LOG_BLOWUP 4   /* blowup 2^0 .. 2^4 */
+#define V3DB_MAX_LOG_LDE 26     /* log_rows + log_blowup <= 26 */
+#define V3DB_MAX_COLS 65535
+
+/* Create a context on HIP device `device`: derives the Poseidon constants from
+ * `poseidon_seed` (as described above; the project's seed is 260303065), builds
+ * the twiddle tables and uploads both (they stay resident until destroy).
+ * `hbm_budget_bytes` caps the device memory the context itself may allocate for
+ * scratch and pooled buffers (0 = no cap). On success *out owns the context. */
+v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budget_bytes, v3db_ctx **out);
+void v3db_ctx_destroy(v3db_ctx *ctx);
+
+/* Message for the last non-OK status returned on this thread ("" if none). The
+ * string stays valid until the next call on this thread. */
+const char *v3db_last_error(void);
+
+/* Host copies of the derived Poseidon constants: rc [30][12], circ [12] (first
+ * row of the circulant) and the number of 12-value draws the MDS search took.
+ * Any output pointer may be NULL. */
+v3db_status v3db_poseidon_constants(const v3db_ctx *ctx, uint64_t *rc_out, uint64_t *circ_out,
+                                    uint32_t *attempts_out);
+
+/* Host only (no device, no context): the constants a context created with
+ * `poseidon_seed` uses, as in v3db_poseidon_constants. Takes about a second the
+ * first time per seed in a process (the exhaustive submatrix check). Returns
+ * UNSUPPORTED if no draw passes within 1000 attempts. */
+v3db_status v3db_derive_poseidon_constants(uint64_t poseidon_seed, uint64_t *rc_out, uint64_t *circ_out,
+                                           uint32_t *attempts_out);
+
+/* Coset low-degree extension.
+ * d_trace [n_cols][2^log_rows] -> d_lde [n_cols][2^(log_rows+log_blowup)].
+ * Column by column: c = iNTT(a), then LDE[k] = sum_j c_j (shift * w_N^k)^j.
+ * layout NATURAL stores out[k] = LDE[k]; BITREV stores out[k] = LDE[rev(k)],
+ * rev reversing log2(N) bits. d_trace and d_lde must not overlap. The context's
+ * scratch (at most 2^(log_rows+log_blowup+3) * min(n_cols, 8) bytes, pooled) is used.
+ * Errors: INVALID_ARG (NULL, n_cols == 0, shift == 0 or >= p, bad layout),
+ * UNSUPPORTED (beyond the limits above), OUT_OF_MEMORY, DEVICE. */
+v3db_status v3db_lde(v3db_ctx *ctx, const uint64_t *d_trace, uint32_t n_cols, uint32_t log_rows,
+                     uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *d_lde,
+                     v3db_stream stream);
+
+/* Poseidon permutation in place on `count` states, row-major [count][12].
+ * Inputs canonical; outputs canonical. count == 0 is a no-op. */
+v3db_status v3db_poseidon_permute(v3db_ctx *ctx, uint64_t *d_states, size_t count, v3db_stream stream);
+
+/* Merkle commitment of the rows of a column-major matrix.
+ * Leaves: digest of row k of d_mat [n_cols][2^log_leaves] (elements d_mat[c][k],
+ * c = 0..n_cols-1, by the sponge above). Levels are built up to height
+ * cap_height; the cap is the 2^cap_height nodes of that level.
+ * d_tree (nullable) receives every level, leaves first:
+ *   [2^L][4], [2^(L-1)][4], ..., [2^h][4]   ((2^(L+1) - 2^h) digests in all).
+ * d_cap receives [2^h][4] (device memory). When d_tree is NULL, scratch from the
+ * context holds the levels.
+ * Errors: INVALID_ARG (NULL d_mat/d_cap, n_cols == 0, cap_height > log_leaves),
+ * UNSUPPORTED (log_leaves > 26), OUT_OF_MEMORY, DEVICE. */
+v3db_status v3db_merkle_commit(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
+                               uint32_t cap_height, uint64_t *d_tree, uint64_t *d_cap, v3db_stream stream);
+
+/* One commit job: LDE of the trace, leaf hashing, Merkle tree up to the cap. */
+typedef struct {
+  const uint64_t *d_trace; /* [n_cols][2^log_rows], device */
+  uint32_t n_cols, log_rows, log_blowup, cap_height;
+  uint64_t shift;
+  v3db_layout layout;
+  uint64_t *d_lde;  /* [n_cols][2^(log_rows+log_blowup)] or NULL: pooled scratch, released after the call's work */
+  uint64_t *d_tree; /* whole tree as in v3db_merkle_commit, or NULL: only the cap is kept */
+  uint64_t *d_cap;  /* [2^cap_height][4], device; required */
+} v3db_commit_job;
+
+/* Commit many independent traces of different shapes in one batched pass: every
+ * phase (interpolation, extension, leaf hashing, each Merkle level) runs as one
+ * launch over the work of all jobs, so small traces share the GPU. The launch
+ * sequence for a given set of shapes is captured once as a HIP graph and
+ * replayed. Scratch for NULL d_lde/d_tree comes from the context and counts
+ * against its HBM budget. Results are identical to committing each job alone.
+ * Errors: as v3db_lde / v3db_merkle_commit for any job (nothing is enqueued),
+ * OUT_OF_MEMORY if the scratch does not fit the budget. */
+v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, v3db_stream stream);
+
+/* Phase timing. While enabled, commit calls record HIP events on their stream
+ * around each phase: V3DB_PHASE_LDE (all extension passes), V3DB_PHASE_LEAF
+ * (row hashing) and V3DB_PHASE_MERKLE (tree levels and cap). v3db_profile_read
+ * waits for the recorded events, adds each phase's elapsed milliseconds and
+ * count of timed intervals into ms_out[3] / count_out[3] (either may be NULL)
+ * and forgets them. Enabling or disabling also forgets pending records. */
+#define V3DB_PHASES 3
+#define V3DB_PHASE_LDE 0
+#define V3DB_PHASE_LEAF 1
+#define V3DB_PHASE_MERKLE 2
+v3db_status v3db_profile_enable(v3db_ctx *ctx, int on);
+v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out);
+
+/* Device bytes of scratch a batch of jobs needs beyond the caller's buffers. */
+size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -70,6 +70,7 @@ def _load():
         "or_ntt": (None, [_U64P, u32, i32]),
         "or_lde": (i32, [_U64P, u32, u32, u32, u64, i32, _U64P]),
         "or_interpolate": (i32, [_U64P, u32, u32, _U64P]),
+        "or_eval_columns": (None, [_U64P, u32, u64, _U64P, u32, _U64P]),
         "or_poseidon_params_init": (i32, [u64, pp]),
         "or_singular_minor_count": (u64, [_U64P]),
         "or_det12": (u64, [_U64P]),
@@ -163,6 +164,15 @@ def lde(trace: np.ndarray, log_blowup: int, shift: int, layout: int = NATURAL) -
     rc = _load().or_lde(_ptr(t), c, log_rows, log_blowup, shift, layout, _ptr(out))
     if rc != 0:
         raise ValueError("oracle lde: invalid arguments")
+    return out
+
+
+def eval_columns(coeffs: np.ndarray, points) -> np.ndarray:
+    """out[c][i] = P_c(points[i]) for the coefficient rows of coeffs [C][n]."""
+    cf = _u64(coeffs)
+    x = _u64(points)
+    out = np.empty((cf.shape[0], x.size), dtype=np.uint64)
+    _load().or_eval_columns(_ptr(cf), cf.shape[0], cf.shape[1], _ptr(x), x.size, _ptr(out))
     return out
 
 

@@ -155,6 +155,19 @@ int or_lde(const uint64_t *trace, uint32_t n_cols, uint32_t log_rows, uint32_t l
   return failed ? -1 : 0;
 }
 
+void or_eval_columns(const uint64_t *coeffs, uint32_t n_cols, uint64_t n, const uint64_t *x,
+                     uint32_t n_points, uint64_t *out) {
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+  for (int64_t c = 0; c < (int64_t)n_cols; c++) {
+    for (int64_t i = 0; i < (int64_t)n_points; i++) {
+      const uint64_t *cf = coeffs + (uint64_t)c * n;
+      uint64_t acc = 0;
+      for (uint64_t j = n; j-- > 0;) acc = or_add(or_mul(acc, x[i]), cf[j]);
+      out[(uint64_t)c * n_points + (uint64_t)i] = acc;
+    }
+  }
+}
+
 /* --------------------------------------------------------------- Poseidon */
 
 /* Index of each 12-bit mask among the masks of the same popcount, in increasing order. */

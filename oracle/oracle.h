@@ -69,6 +69,11 @@ int or_lde(const uint64_t *trace, uint32_t n_cols, uint32_t log_rows, uint32_t l
 /* Interpolation only: coefficients c (natural order) of each column, [n_cols][2^log_rows]. */
 int or_interpolate(const uint64_t *trace, uint32_t n_cols, uint32_t log_rows, uint64_t *coeffs);
 
+/* Horner evaluation: out[c][i] = sum_j coeffs[c][j] * x[i]^j for each column c
+ * of coeffs [n_cols][n] and each of the n_points points. */
+void or_eval_columns(const uint64_t *coeffs, uint32_t n_cols, uint64_t n, const uint64_t *x,
+                     uint32_t n_points, uint64_t *out);
+
 /* ---- Poseidon (t = 12, x^7) ---- */
 typedef struct {
   uint64_t seed;

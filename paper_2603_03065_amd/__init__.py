@@ -1,0 +1,251 @@
+"""Python binding for libv3db (trace commitment on MI355X / gfx950).
+
+Thin argument marshalling over the C ABI in include/v3db.h: every step of the
+commitment runs in the library's HIP kernels. PyTorch supplies device memory
+and streams only: field elements live in int64 tensors used as raw 64-bit words
+(values >= 2^63 appear negative in torch and are the same bits), passed to the
+library as data pointers, with the current torch stream as the HIP stream.
+
+If libv3db.so has not been built this module raises on first use; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libv3db.so")
+
+P = 0xFFFFFFFF00000001
+POSEIDON_SEED = 260303065
+NATURAL, BITREV = 0, 1
+
+_STATUS = {
+    0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "NONCANONICAL",
+    4: "OUT_OF_MEMORY", 5: "DEVICE", 6: "BUSY",
+}
+
+
+class V3dbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"v3db {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [
+        ("d_trace", ctypes.c_void_p),
+        ("n_cols", ctypes.c_uint32),
+        ("log_rows", ctypes.c_uint32),
+        ("log_blowup", ctypes.c_uint32),
+        ("cap_height", ctypes.c_uint32),
+        ("shift", ctypes.c_uint64),
+        ("layout", ctypes.c_int),
+        ("d_lde", ctypes.c_void_p),
+        ("d_tree", ctypes.c_void_p),
+        ("d_cap", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libv3db.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (its libamdhip64 must be the one the library binds to)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python paper_2603_03065_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+    sig = {
+        "v3db_ctx_create": (i32, [i32, u64, sz, ctypes.POINTER(vp)]),
+        "v3db_ctx_destroy": (None, [vp]),
+        "v3db_last_error": (ctypes.c_char_p, []),
+        "v3db_poseidon_constants": (i32, [vp, vp, vp, ctypes.POINTER(u32)]),
+        "v3db_derive_poseidon_constants": (i32, [u64, vp, vp, ctypes.POINTER(u32)]),
+        "v3db_lde": (i32, [vp, vp, u32, u32, u32, u64, i32, vp, vp]),
+        "v3db_poseidon_permute": (i32, [vp, vp, sz, vp]),
+        "v3db_merkle_commit": (i32, [vp, vp, u32, u32, u32, vp, vp, vp]),
+        "v3db_commit_batch": (i32, [vp, ctypes.POINTER(_Job), sz, vp]),
+        "v3db_commit_batch_scratch_bytes": (sz, [ctypes.POINTER(_Job), sz]),
+        "v3db_profile_enable": (i32, [vp, i32]),
+        "v3db_profile_read": (i32, [vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise V3dbError(status, lib().v3db_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    assert t.dtype == torch.int64 and t.is_cuda and t.is_contiguous(), "expected a contiguous int64 CUDA tensor"
+    return t.data_ptr()
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """uint64 numpy array -> int64 torch tensor on the device (same bits)."""
+    import torch
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """int64 torch tensor -> uint64 numpy array (same bits)."""
+    return t.detach().cpu().contiguous().numpy().view(np.uint64)
+
+
+def derive_poseidon_constants(seed: int = POSEIDON_SEED):
+    """Host-only: (rc [30][12], circ [12], attempts) a context with this seed uses."""
+    rc = np.zeros((30, 12), dtype=np.uint64)
+    circ = np.zeros(12, dtype=np.uint64)
+    att = ctypes.c_uint32(0)
+    _check(lib().v3db_derive_poseidon_constants(seed, rc.ctypes.data, circ.ctypes.data, ctypes.byref(att)))
+    return rc, circ, int(att.value)
+
+
+@dataclass
+class Job:
+    """One trace to commit; tensors are int64 on the device."""
+    trace: object                      # [n_cols][2^log_rows]
+    log_blowup: int = 3
+    cap_height: int = 0
+    shift: int = 7
+    layout: int = NATURAL
+    lde: object = None                 # [n_cols][N] or None (scratch)
+    tree: object = None                # [2N - 2^h][4] or None
+    cap: object = None                 # [2^h][4]; allocated if None
+
+
+class Context:
+    """A device context: resident Poseidon constants and twiddle tables."""
+
+    def __init__(self, device: int = 0, seed: int = POSEIDON_SEED, hbm_budget: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.v3db_ctx_create(device, seed, hbm_budget, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.seed = seed
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().v3db_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def poseidon_constants(self):
+        rc = np.zeros((30, 12), dtype=np.uint64)
+        circ = np.zeros(12, dtype=np.uint64)
+        att = ctypes.c_uint32(0)
+        _check(lib().v3db_poseidon_constants(self._h, rc.ctypes.data, circ.ctypes.data, ctypes.byref(att)))
+        return rc, circ, int(att.value)
+
+    def lde(self, trace, log_blowup: int, shift: int = 7, layout: int = NATURAL, out=None, stream=None):
+        import torch
+        n_cols, n = trace.shape
+        log_rows = n.bit_length() - 1
+        if 1 << log_rows != n:
+            raise ValueError("rows must be a power of two")
+        if out is None:
+            out = torch.empty((n_cols, n << log_blowup), dtype=torch.int64, device=trace.device)
+        _check(lib().v3db_lde(self._h, _ptr(trace), n_cols, log_rows, log_blowup, shift, layout, _ptr(out),
+                              _stream(stream)))
+        return out
+
+    def poseidon_permute(self, states, stream=None):
+        """In place on a [count][12] tensor."""
+        count = states.numel() // 12
+        _check(lib().v3db_poseidon_permute(self._h, _ptr(states), count, _stream(stream)))
+        return states
+
+    def merkle_commit(self, mat, cap_height: int, tree=None, cap=None, stream=None):
+        import torch
+        n_cols, nl = mat.shape
+        log_leaves = nl.bit_length() - 1
+        if 1 << log_leaves != nl:
+            raise ValueError("leaf count must be a power of two")
+        if cap is None:
+            cap = torch.empty((1 << cap_height, 4), dtype=torch.int64, device=mat.device)
+        _check(lib().v3db_merkle_commit(self._h, _ptr(mat), n_cols, log_leaves, cap_height, _ptr(tree), _ptr(cap),
+                                        _stream(stream)))
+        return cap
+
+    @staticmethod
+    def _jobs(jobs: Sequence[Job]):
+        import torch
+        arr = (_Job * len(jobs))()
+        for i, j in enumerate(jobs):
+            n_cols, n = j.trace.shape
+            log_rows = n.bit_length() - 1
+            if 1 << log_rows != n:
+                raise ValueError("rows must be a power of two")
+            if j.cap is None:
+                j.cap = torch.empty((1 << j.cap_height, 4), dtype=torch.int64, device=j.trace.device)
+            arr[i] = _Job(_ptr(j.trace), n_cols, log_rows, j.log_blowup, j.cap_height, j.shift, j.layout,
+                          _ptr(j.lde), _ptr(j.tree), _ptr(j.cap))
+        return arr
+
+    def commit_batch(self, jobs: Sequence[Job], stream=None):
+        arr = self._jobs(jobs)
+        _check(lib().v3db_commit_batch(self._h, arr, len(jobs), _stream(stream)))
+        return [j.cap for j in jobs]
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().v3db_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{phase: (milliseconds, intervals)} since the last read, for lde / leaf / merkle."""
+        ms = np.zeros(3, dtype=np.float64)
+        cnt = np.zeros(3, dtype=np.uint64)
+        _check(lib().v3db_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(("lde", "leaf", "merkle"))}
+
+    def commit(self, job: Job, stream=None):
+        return self.commit_batch([job], stream)[0]
+
+
+def commit_batch_scratch_bytes(jobs: Sequence[Job]) -> int:
+    arr = Context._jobs(jobs)
+    return int(lib().v3db_commit_batch_scratch_bytes(arr, len(jobs)))

@@ -1,0 +1,319 @@
+// C-ABI entry points: context, errors, argument checks, scratch, and the
+// single-trace calls. The batched path lives in batch.hip.
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "internal.h"
+
+namespace v3db {
+
+static thread_local std::string g_last_error;
+
+v3db_status set_error(v3db_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+v3db_status hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return V3DB_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return set_error(V3DB_ERR_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+  return set_error(V3DB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+v3db_status ctx_alloc(v3db_ctx *ctx, void **ptr, size_t bytes, const char *what) {
+  if (ctx->budget && ctx->allocated + bytes > ctx->budget)
+    return set_error(V3DB_ERR_OUT_OF_MEMORY, std::string(what) + ": context HBM budget exceeded (" +
+                                                 std::to_string(ctx->allocated + bytes) + " > " +
+                                                 std::to_string(ctx->budget) + " bytes)");
+  hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(V3DB_ERR_OUT_OF_MEMORY, std::string(what) + ": hipMalloc of " + std::to_string(bytes) +
+                                                 " bytes failed: " + hipGetErrorString(e));
+  }
+  ctx->allocated += bytes;
+  return V3DB_OK;
+}
+
+void ctx_free(v3db_ctx *ctx, void *ptr, size_t bytes) {
+  if (!ptr) return;
+  (void)hipFree(ptr);
+  ctx->allocated -= bytes;
+}
+
+v3db_status ctx_scratch(v3db_ctx *ctx, hipStream_t stream, size_t bytes, void **out) {
+  ScratchBuf &sb = ctx->scratch[(void *)stream];
+  if (sb.bytes < bytes) {
+    if (sb.ptr) {
+      // the old buffer may still be read by queued work on this stream
+      hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return hip_check(e, "scratch resize sync");
+      ctx_free(ctx, sb.ptr, sb.bytes);
+      sb.ptr = nullptr;
+      sb.bytes = 0;
+    }
+    v3db_status st = ctx_alloc(ctx, &sb.ptr, bytes, "scratch");
+    if (st != V3DB_OK) return st;
+    sb.bytes = bytes;
+  }
+  *out = sb.ptr;
+  return V3DB_OK;
+}
+
+hipEvent_t prof_mark(v3db_ctx *ctx, hipStream_t stream) {
+  if (!ctx->profiling) return nullptr;
+  hipEvent_t e = nullptr;
+  if (!ctx->event_pool.empty()) {
+    e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, stream) != hipSuccess) {
+    ctx->event_pool.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b) {
+  if (a && b) ctx->prof_pending.push_back({phase, {a, b}});
+}
+
+static void prof_drop(v3db_ctx *ctx) {
+  for (auto &r : ctx->prof_pending) {
+    ctx->event_pool.push_back(r.second.first);
+    ctx->event_pool.push_back(r.second.second);
+  }
+  ctx->prof_pending.clear();
+}
+
+static bool validate_inputs_enabled() {
+  const char *v = getenv("V3DB_VALIDATE");
+  return v && v[0] == '1';
+}
+
+// Returns V3DB_OK or sets the error for an invalid LDE shape.
+static v3db_status check_lde_args(const void *trace, uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup,
+                                  uint64_t shift, int layout, const void *lde) {
+  if (!trace || !lde) return set_error(V3DB_ERR_INVALID_ARG, "lde: NULL trace or output pointer");
+  if (n_cols == 0) return set_error(V3DB_ERR_INVALID_ARG, "lde: n_cols must be > 0");
+  if (shift == 0 || shift >= gl::P) return set_error(V3DB_ERR_INVALID_ARG, "lde: shift must be in [1, p)");
+  if (layout != V3DB_LAYOUT_NATURAL && layout != V3DB_LAYOUT_BITREV)
+    return set_error(V3DB_ERR_INVALID_ARG, "lde: unknown layout");
+  if (n_cols > V3DB_MAX_COLS) return set_error(V3DB_ERR_UNSUPPORTED, "lde: more than 65535 columns");
+  if (log_rows > V3DB_MAX_LOG_ROWS || log_blowup > V3DB_MAX_LOG_BLOWUP || log_rows + log_blowup > V3DB_MAX_LOG_LDE)
+    return set_error(V3DB_ERR_UNSUPPORTED, "lde: log_rows <= 24, log_blowup <= 4 and their sum <= 26 required");
+  return V3DB_OK;
+}
+
+static v3db_status check_merkle_args(const void *mat, uint32_t n_cols, uint32_t log_leaves, uint32_t cap_height,
+                                     const void *cap) {
+  if (!mat || !cap) return set_error(V3DB_ERR_INVALID_ARG, "merkle: NULL matrix or cap pointer");
+  if (n_cols == 0) return set_error(V3DB_ERR_INVALID_ARG, "merkle: n_cols must be > 0");
+  if (cap_height > log_leaves) return set_error(V3DB_ERR_INVALID_ARG, "merkle: cap_height > log_leaves");
+  if (log_leaves > V3DB_MAX_LOG_LDE) return set_error(V3DB_ERR_UNSUPPORTED, "merkle: log_leaves > 26");
+  if (n_cols > V3DB_MAX_COLS) return set_error(V3DB_ERR_UNSUPPORTED, "merkle: more than 65535 columns");
+  return V3DB_OK;
+}
+
+// Optional input check (V3DB_VALIDATE=1): counts elements >= p.
+__global__ void k_count_noncanonical(const uint64_t *__restrict__ x, size_t n, unsigned int *bad) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  unsigned int local = 0;
+  for (; i < n; i += stride) local += x[i] >= gl::P;
+  if (local) atomicAdd(bad, local);
+}
+
+static v3db_status check_canonical(v3db_ctx *ctx, const uint64_t *x, size_t n, hipStream_t stream) {
+  if (!validate_inputs_enabled() || n == 0) return V3DB_OK;
+  unsigned int *d_bad = nullptr;
+  v3db_status st = ctx_alloc(ctx, (void **)&d_bad, sizeof(unsigned int), "validation flag");
+  if (st != V3DB_OK) return st;
+  unsigned int bad = 0;
+  hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(unsigned int), stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_count_noncanonical, dim3(1024), dim3(256), 0, stream, x, n, d_bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  ctx_free(ctx, d_bad, sizeof(unsigned int));
+  if (e != hipSuccess) return hip_check(e, "validation");
+  if (bad) return set_error(V3DB_ERR_NONCANONICAL, std::to_string(bad) + " input elements are >= p");
+  return V3DB_OK;
+}
+
+}  // namespace v3db
+
+using namespace v3db;
+
+extern "C" {
+
+const char *v3db_last_error(void) { return g_last_error.c_str(); }
+
+v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budget_bytes, v3db_ctx **out) {
+  clear_error();
+  if (!out) return set_error(V3DB_ERR_INVALID_ARG, "ctx_create: NULL out");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return set_error(V3DB_ERR_DEVICE, "ctx_create: no HIP device");
+  if (device < 0 || device >= ndev) return set_error(V3DB_ERR_INVALID_ARG, "ctx_create: device out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_check(e, "ctx_create: hipSetDevice");
+  v3db_ctx *ctx = new v3db_ctx();
+  ctx->device = device;
+  ctx->seed = poseidon_seed;
+  ctx->budget = hbm_budget_bytes;
+  if (!derive_poseidon(poseidon_seed, ctx->pos, ctx->mds_attempts)) {
+    delete ctx;
+    return set_error(V3DB_ERR_UNSUPPORTED, "ctx_create: no MDS circulant found in 1000 draws");
+  }
+  v3db_status st = ctx_alloc(ctx, (void **)&ctx->d_pos, ROUNDS * WIDTH * 8, "Poseidon constants");
+  if (st == V3DB_OK)
+    st = hip_check(hipMemcpy(ctx->d_pos, ctx->pos.rc, ROUNDS * WIDTH * 8, hipMemcpyHostToDevice),
+                   "upload Poseidon constants");
+  if (st == V3DB_OK) st = build_twiddles(ctx);
+  if (st != V3DB_OK) {
+    v3db_ctx_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return V3DB_OK;
+}
+
+void v3db_ctx_destroy(v3db_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  prof_drop(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  ctx->event_pool.clear();
+  for (auto &kv : ctx->scratch) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
+  ctx->scratch.clear();
+  free_twiddles(ctx);
+  ctx_free(ctx, ctx->d_pos, ROUNDS * WIDTH * 8);
+  delete ctx;
+}
+
+v3db_status v3db_poseidon_constants(const v3db_ctx *ctx, uint64_t *rc_out, uint64_t *circ_out,
+                                    uint32_t *attempts_out) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "poseidon_constants: NULL ctx");
+  if (rc_out) memcpy(rc_out, ctx->pos.rc, sizeof(ctx->pos.rc));
+  if (circ_out)
+    for (int i = 0; i < WIDTH; i++) circ_out[i] = ctx->pos.circ[i];
+  if (attempts_out) *attempts_out = ctx->mds_attempts;
+  return V3DB_OK;
+}
+
+v3db_status v3db_profile_enable(v3db_ctx *ctx, int on) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "profile_enable: NULL ctx");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  prof_drop(ctx);
+  ctx->profiling = on != 0;
+  return V3DB_OK;
+}
+
+v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "profile_read: NULL ctx");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  v3db_status st = V3DB_OK;
+  for (auto &r : ctx->prof_pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.second.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.second.first, r.second.second);
+    if (e != hipSuccess) {
+      st = hip_check(e, "profile_read");
+      break;
+    }
+    if (ms_out) ms_out[r.first] += ms;
+    if (count_out) count_out[r.first] += 1;
+  }
+  prof_drop(ctx);
+  return st;
+}
+
+v3db_status v3db_derive_poseidon_constants(uint64_t poseidon_seed, uint64_t *rc_out, uint64_t *circ_out,
+                                           uint32_t *attempts_out) {
+  clear_error();
+  PoseidonTables t;
+  uint32_t attempts = 0;
+  if (!derive_poseidon(poseidon_seed, t, attempts))
+    return set_error(V3DB_ERR_UNSUPPORTED, "derive_poseidon_constants: no MDS circulant found in 1000 draws");
+  if (rc_out) memcpy(rc_out, t.rc, sizeof(t.rc));
+  if (circ_out)
+    for (int i = 0; i < WIDTH; i++) circ_out[i] = t.circ[i];
+  if (attempts_out) *attempts_out = attempts;
+  return V3DB_OK;
+}
+
+v3db_status v3db_lde(v3db_ctx *ctx, const uint64_t *d_trace, uint32_t n_cols, uint32_t log_rows,
+                     uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *d_lde,
+                     v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "lde: NULL ctx");
+  v3db_status st = check_lde_args(d_trace, n_cols, log_rows, log_blowup, shift, layout, d_lde);
+  if (st != V3DB_OK) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  st = check_canonical(ctx, d_trace, size_t(n_cols) << log_rows, s);
+  if (st != V3DB_OK) return st;
+  void *z = nullptr;
+  st = ctx_scratch(ctx, s, lde_scratch_bytes(n_cols, log_rows, log_blowup), &z);
+  if (st != V3DB_OK) return st;
+  return enqueue_lde(ctx, d_trace, n_cols, log_rows, log_blowup, shift, layout, d_lde, (uint64_t *)z, s);
+}
+
+v3db_status v3db_poseidon_permute(v3db_ctx *ctx, uint64_t *d_states, size_t count, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "permute: NULL ctx");
+  if (count == 0) return V3DB_OK;
+  if (!d_states) return set_error(V3DB_ERR_INVALID_ARG, "permute: NULL states");
+  if (count > (size_t(1) << 40)) return set_error(V3DB_ERR_UNSUPPORTED, "permute: count too large");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  v3db_status st = check_canonical(ctx, d_states, count * WIDTH, s);
+  if (st != V3DB_OK) return st;
+  return enqueue_permute(ctx, d_states, count, s);
+}
+
+v3db_status v3db_merkle_commit(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
+                               uint32_t cap_height, uint64_t *d_tree, uint64_t *d_cap, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "merkle_commit: NULL ctx");
+  v3db_status st = check_merkle_args(d_mat, n_cols, log_leaves, cap_height, d_cap);
+  if (st != V3DB_OK) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  st = check_canonical(ctx, d_mat, size_t(n_cols) << log_leaves, s);
+  if (st != V3DB_OK) return st;
+  uint64_t *tree = d_tree;
+  if (!tree) {
+    const size_t digests = (size_t(2) << log_leaves) - (size_t(1) << cap_height);
+    void *p = nullptr;
+    st = ctx_scratch(ctx, s, digests * DIGEST * 8, &p);
+    if (st != V3DB_OK) return st;
+    tree = (uint64_t *)p;
+  }
+  st = enqueue_leaf_hash(ctx, d_mat, n_cols, log_leaves, tree, s);
+  if (st != V3DB_OK) return st;
+  return enqueue_merkle_levels(ctx, tree, log_leaves, cap_height, d_cap, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Poseidon constants derived from a seed (host side, once per context).
+//
+// Stream: SplitMix64 (Steele, Lea, Flood 2014), output i = finaliser(seed + (i+1) * golden gamma).
+// Round constants: the first 360 outputs below p, round-major. MDS: a circulant
+// whose first row is a_j = 1 + (z mod 255) over the next 12 outputs, redrawn
+// until every square submatrix is nonsingular mod p.
+#include <string.h>
+
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+
+namespace v3db {
+
+uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Nonsingularity of a k x k matrix over F_p by fraction-free Gaussian
+// elimination: row_r <- pivot * row_r - a_r * row_pivot keeps the rank and
+// needs no inverses.
+static bool nonsingular(uint64_t m[WIDTH][WIDTH], int k) {
+  for (int col = 0; col < k; col++) {
+    int piv = -1;
+    for (int r = col; r < k; r++)
+      if (m[r][col] != 0) {
+        piv = r;
+        break;
+      }
+    if (piv < 0) return false;
+    if (piv != col)
+      for (int c = 0; c < k; c++) {
+        uint64_t t = m[col][c];
+        m[col][c] = m[piv][c];
+        m[piv][c] = t;
+      }
+    const uint64_t pv = m[col][col];
+    for (int r = col + 1; r < k; r++) {
+      const uint64_t f = m[r][col];
+      if (f == 0) continue;
+      for (int c = col; c < k; c++) m[r][c] = gl::sub(gl::mul(m[r][c], pv), gl::mul(m[col][c], f));
+    }
+  }
+  return true;
+}
+
+// A circulant satisfies M[i+s][j+s] = M[i][j] (indices mod 12), so the
+// submatrix on (R, C) equals, up to a reordering of rows and columns, the one on
+// (R - s, C - s). Shifting by min(R) leaves 0 in R: checking only row sets that
+// contain row 0 covers every square submatrix.
+bool circulant_is_mds(const uint32_t circ[WIDTH]) {
+  uint64_t sub[WIDTH][WIDTH];
+  int rows[WIDTH], cols[WIDTH];
+  for (uint32_t R = 1; R < (1u << WIDTH); R += 2) {  // bit 0 set
+    const int k = __builtin_popcount(R);
+    int nr = 0;
+    for (int i = 0; i < WIDTH; i++)
+      if (R >> i & 1) rows[nr++] = i;
+    for (uint32_t C = 1; C < (1u << WIDTH); C++) {
+      if (__builtin_popcount(C) != k) continue;
+      int nc = 0;
+      for (int j = 0; j < WIDTH; j++)
+        if (C >> j & 1) cols[nc++] = j;
+      for (int a = 0; a < k; a++)
+        for (int b = 0; b < k; b++) sub[a][b] = circ[(cols[b] - rows[a] + WIDTH) % WIDTH];
+      if (!nonsingular(sub, k)) return false;
+    }
+  }
+  return true;
+}
+
+bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts) {
+  // The search costs ~1e8 field operations; cache results per seed for the process.
+  static std::mutex mu;
+  static std::map<uint64_t, std::pair<PoseidonTables, uint32_t>> cache;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(seed);
+    if (it != cache.end()) {
+      out = it->second.first;
+      attempts = it->second.second;
+      return true;
+    }
+  }
+  PoseidonTables t;
+  memset(&t, 0, sizeof(t));
+  uint64_t i = 0;
+  for (int r = 0; r < ROUNDS; r++)
+    for (int j = 0; j < WIDTH; j++) {
+      uint64_t z;
+      do z = splitmix64(seed, i++);
+      while (z >= gl::P);
+      t.rc[r][j] = z;
+    }
+  for (uint32_t attempt = 1; attempt <= 1000; attempt++) {
+    for (int j = 0; j < WIDTH; j++) t.circ[j] = 1 + (uint32_t)(splitmix64(seed, i++) % 255);
+    if (circulant_is_mds(t.circ)) {
+      out = t;
+      attempts = attempt;
+      std::lock_guard<std::mutex> g(mu);
+      cache[seed] = {t, attempt};
+      return true;
+    }
+  }
+  return false;
+}
+
+}  // namespace v3db

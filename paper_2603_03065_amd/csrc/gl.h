@@ -1,0 +1,91 @@
+// Goldilocks field arithmetic, p = 2^64 - 2^32 + 1, for gfx950 VALU and the host.
+//
+// No Montgomery form: a 128-bit product x = hi*2^64 + lo with hi = hh*2^32 + hl
+// reduces through 2^64 = 2^32 - 1 (mod p) and 2^96 = -1 (mod p) to
+//   x = lo - hh + hl*(2^32 - 1)   (mod p),
+// one subtraction and one addition with carry fix-ups. Products are built from
+// four 32x32->64 multiply-adds (v_mad_u64_u32 is full rate on gfx950).
+//
+// Two kinds of values appear:
+//   canonical   in [0, p): every public input and output, and the NTT data;
+//   relaxed     in [0, 2^64): Poseidon state between rounds (reduced at the end).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GL_HD __host__ __device__ __forceinline__
+
+namespace gl {
+
+constexpr uint64_t P = 0xffffffff00000001ull;
+constexpr uint64_t EPS = 0xffffffffull;  // 2^64 mod p
+
+// 64x64 -> 128 product from 32-bit halves.
+GL_HD void mul_wide(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
+  uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  uint64_t t = (uint64_t)a0 * b0;
+  uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+  uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+  hi = (uint64_t)a1 * b1 + (u >> 32) + (v >> 32);
+  lo = (v << 32) | (uint32_t)t;
+}
+
+// Reduce hi*2^64 + lo (any 128-bit value) to a relaxed value in [0, 2^64).
+GL_HD uint64_t reduce128(uint64_t lo, uint64_t hi) {
+  uint64_t hh = hi >> 32, hl = hi & EPS;
+  uint64_t t0 = lo - hh;
+  if (lo < hh) t0 -= EPS;            // borrowed 2^64 = EPS (mod p); t0 >= 2^64 - 2^32 here
+  uint64_t t1 = (hl << 32) - hl;     // hl * (2^32 - 1)
+  uint64_t t2 = t0 + t1;
+  if (t2 < t1) t2 += EPS;            // carried 2^64; cannot carry again
+  return t2;
+}
+
+GL_HD uint64_t canon(uint64_t x) { return x >= P ? x - P : x; }
+
+// relaxed * relaxed -> relaxed
+GL_HD uint64_t mul_r(uint64_t a, uint64_t b) {
+  uint64_t lo, hi;
+  mul_wide(a, b, lo, hi);
+  return reduce128(lo, hi);
+}
+
+// canonical results
+GL_HD uint64_t mul(uint64_t a, uint64_t b) { return canon(mul_r(a, b)); }
+
+GL_HD uint64_t add(uint64_t a, uint64_t b) {  // a, b canonical
+  uint64_t s = a + b;
+  if (s < a) return s + EPS;         // a + b - 2^64 + EPS < p
+  return canon(s);
+}
+
+GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical
+  uint64_t d = a - b;
+  if (a < b) d -= EPS;               // a - b + p = d - 2^64 + p = d - EPS
+  return d;
+}
+
+// relaxed a + canonical b -> relaxed
+GL_HD uint64_t add_r(uint64_t a, uint64_t b) {
+  uint64_t s = a + b;
+  if (s < b) s += EPS;               // a + b - 2^64 < p - 1, so no second carry
+  return s;
+}
+
+GL_HD uint64_t pow(uint64_t a, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = mul(r, a);
+    a = mul(a, a);
+    e >>= 1;
+  }
+  return r;
+}
+
+GL_HD uint64_t inv(uint64_t a) { return pow(a, P - 2); }
+
+// w_{2^k} = 7^((p-1)/2^k): 7 generates the multiplicative group.
+inline uint64_t root_of_unity(uint32_t log_n) { return pow(7, (P - 1) >> log_n); }
+
+}  // namespace gl

@@ -1,0 +1,109 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/v3db.h"
+#include "gl.h"
+
+namespace v3db {
+
+constexpr int WIDTH = 12, RATE = 8, DIGEST = 4, ROUNDS = 30, FULL_HALF = 4;
+constexpr int TW_LOG = 26;        // largest transform, 2^26 points
+constexpr int TW_HALF = 13;       // two-level twiddle table: 2^13 x 2^13
+constexpr int DFT_LOG_MAX = 12;   // largest in-LDS sub-transform, 4096 points
+
+// Round constants and MDS first row, as the kernels consume them.
+struct PoseidonTables {
+  uint64_t rc[ROUNDS][WIDTH];
+  uint32_t circ[WIDTH];
+};
+
+// Device twiddle tables, built once per context.
+struct Twiddles {
+  uint64_t *fwd_lo, *fwd_hi;   // w^i and w^(2^13 i), w = w_{2^26}, i < 2^13
+  uint64_t *inv_lo, *inv_hi;   // same for w^-1
+  uint64_t *dft_fwd, *dft_inv; // w_4096^t and w_4096^-t, t < 2048
+};
+
+// Per-shape LDE tables: see ntt.hip.
+struct LdePlan {
+  uint32_t log_rows, log_blowup, L1, L2;
+  uint64_t shift;
+  uint64_t *d_twist;  // [B][n2]: (shift^n1 * w_{B n2}^r)^j
+  uint64_t *d_scale;  // [n1]: n^-1 * shift^k1
+};
+
+struct ScratchBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace v3db
+
+struct v3db_ctx {
+  int device = 0;
+  uint64_t seed = 0;
+  size_t budget = 0;       // 0 = unlimited
+  size_t allocated = 0;    // bytes currently held by this context
+  uint32_t mds_attempts = 0;
+  v3db::PoseidonTables pos{};
+  uint64_t *d_pos = nullptr;  // device copy of pos.rc (flat 360) followed by circ as u64 (12)
+  v3db::Twiddles tw{};
+  std::map<std::tuple<uint32_t, uint32_t, uint64_t>, v3db::LdePlan> plans;
+  std::map<void *, v3db::ScratchBuf> scratch;  // per stream
+  // phase timing (v3db_profile_*): event pairs per phase, recycled through a pool
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+  std::vector<hipEvent_t> event_pool;
+  std::mutex mu;
+};
+
+namespace v3db {
+
+// Error reporting (thread-local message).
+v3db_status set_error(v3db_status st, const std::string &msg);
+void clear_error();
+v3db_status hip_check(hipError_t e, const char *what);
+
+// Context-owned device memory, counted against the budget.
+v3db_status ctx_alloc(v3db_ctx *ctx, void **ptr, size_t bytes, const char *what);
+void ctx_free(v3db_ctx *ctx, void *ptr, size_t bytes);
+// Per-stream scratch of at least `bytes` (grown as needed).
+v3db_status ctx_scratch(v3db_ctx *ctx, hipStream_t stream, size_t bytes, void **out);
+
+// Host-side constant derivation (constants.cpp).
+uint64_t splitmix64(uint64_t seed, uint64_t i);
+bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts);
+bool circulant_is_mds(const uint32_t circ[WIDTH]);
+
+// Tables (ntt.hip).
+v3db_status build_twiddles(v3db_ctx *ctx);
+void free_twiddles(v3db_ctx *ctx);
+v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out);
+
+// Enqueue an LDE (ntt.hip). Arguments already validated.
+constexpr uint32_t LDE_CHUNK_COLS = 8;  // columns whose Z scratch is live at once
+size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup);
+v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, uint32_t log_rows,
+                        uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *lde,
+                        uint64_t *z, hipStream_t stream);
+
+// Phase timing: returns an event recorded on `stream` (or nullptr when not profiling).
+hipEvent_t prof_mark(v3db_ctx *ctx, hipStream_t stream);
+void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
+
+// Poseidon work (poseidon.hip).
+v3db_status enqueue_permute(v3db_ctx *ctx, uint64_t *states, size_t count, hipStream_t stream);
+v3db_status enqueue_leaf_hash(v3db_ctx *ctx, const uint64_t *mat, uint32_t n_cols, uint32_t log_leaves,
+                              uint64_t *digests, hipStream_t stream);
+v3db_status enqueue_merkle_levels(v3db_ctx *ctx, uint64_t *tree, uint32_t log_leaves, uint32_t cap_height,
+                                  uint64_t *cap, hipStream_t stream);
+
+}  // namespace v3db

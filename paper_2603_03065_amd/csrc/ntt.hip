@@ -1,0 +1,371 @@
+// Coset low-degree extension on gfx950.
+//
+// For a column a of n = 2^L values (a_i = P(w_n^i)), the extension to N = B*n
+// points is LDE[k] = P(s * w_N^k) = sum_j c_j (s w_N^k)^j with c = iNTT_n(a).
+// It runs as three LDS-tiled passes of a four-step factorisation, n = n1*n2:
+//
+//   pass 1  (interpolation, first half)   j = j1*n2 + j2, k = k1 + n1*k2
+//           Y[k1][j2] = w_n^(-j2 k1) * sum_j1 a[j1 n2 + j2] w_n1^(-j1 k1)
+//   pass 2  per residue k1: c'[k2] = sum_j2 Y[k1][j2] w_n2^(-j2 k2)   (= n c[k1 + n1 k2])
+//           then, for each coset row e = r + B*m1 (r < B, m1 < n2), a blowup-B
+//           extension of that residue sequence with shift s^n1:
+//           Z[e][k1] = n^-1 s^k1 w_N^(k1 e) * sum_k2 c'[k2] (s^n1 w_(B n2)^r)^k2 w_n2^(k2 m1)
+//   pass 3  per row e: LDE[e + B n2 m2] = sum_k1 Z[e][k1] w_n1^(k1 m2)
+//
+// (LDE[e + B n2 m2] = sum_k1 w_n1^(k1 m2) s^k1 w_N^(k1 e) sum_k2 c[k1+n1 k2]
+//  (s^n1)^k2 w_(B n2)^(k2 e) follows from j = k1 + n1 k2 and k = e + B n2 m2.)
+//
+// Each pass moves tiles of T adjacent columns/rows so global accesses are runs
+// of T*8 bytes, does its sub-transforms in LDS (radix-2 decimation-in-frequency
+// for natural -> bit-reversed, decimation-in-time for bit-reversed -> natural),
+// and applies the twiddles on the way out. Pass 1 writes Y into the first n
+// entries of the output column (free until pass 3); pass 2 writes Z (B*n per
+// column) to scratch, a chunk of columns at a time; pass 3 writes the output in
+// natural order (runs of T) or bit-reversed order (contiguous rows).
+#include "internal.h"
+
+namespace v3db {
+
+namespace {
+
+constexpr int THREADS = 256;
+constexpr int DFT_N = 1 << DFT_LOG_MAX;  // 4096
+constexpr int TILE_ELEMS = 8192;         // T * M per tile
+constexpr int MAX_PER_THREAD = TILE_ELEMS / THREADS;
+
+__device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
+  return bits ? (__brev(x) >> (32 - bits)) : 0u;
+}
+
+// w^e for e < 2^26 from the two-level table (w = w_{2^26} or its inverse).
+__device__ __forceinline__ uint64_t tw_pow(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
+                                           uint32_t e) {
+  return gl::mul(hi[e >> TW_HALF], lo[e & ((1u << TW_HALF) - 1)]);
+}
+
+// Radix-2 decimation in frequency along each of T rows of length 2^logM (row
+// stride rs) in LDS: natural order in, bit-reversed order out. tw = w_4096^t.
+__device__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  if (logM == 0) return;
+  const int half = 1 << (logM - 1);
+  const int nb = T * half;
+  for (int logh = logM - 1; logh >= 0; --logh) {
+    const int h = 1 << logh;
+    const int tws = DFT_N >> (logh + 1);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int t = b >> (logM - 1);
+      const int q = b & (half - 1);
+      const int i = q & (h - 1);
+      const int i0 = t * rs + ((q >> logh) << (logh + 1)) + i;
+      const uint64_t u = sh[i0], v = sh[i0 + h];
+      sh[i0] = gl::add(u, v);
+      const uint64_t d = gl::sub(u, v);
+      sh[i0 + h] = i ? gl::mul(d, tw[i * tws]) : d;
+    }
+    __syncthreads();
+  }
+}
+
+// Radix-2 decimation in time: bit-reversed order in, natural order out.
+__device__ void dit_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  if (logM == 0) return;
+  const int half = 1 << (logM - 1);
+  const int nb = T * half;
+  for (int logh = 0; logh < logM; ++logh) {
+    const int h = 1 << logh;
+    const int tws = DFT_N >> (logh + 1);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int t = b >> (logM - 1);
+      const int q = b & (half - 1);
+      const int i = q & (h - 1);
+      const int i0 = t * rs + ((q >> logh) << (logh + 1)) + i;
+      const uint64_t u = sh[i0];
+      uint64_t v = sh[i0 + h];
+      if (i) v = gl::mul(v, tw[i * tws]);
+      sh[i0] = gl::add(u, v);
+      sh[i0 + h] = gl::sub(u, v);
+    }
+    __syncthreads();
+  }
+}
+
+struct Shape {
+  int L, b, L1, L2;   // log n, log blowup, log n1, log n2
+  int logT1, logT2, logT3;
+};
+
+// Pass 1: tile = T consecutive j2 of one column.
+__global__ void __launch_bounds__(THREADS) k_lde_pass1(const uint64_t *__restrict__ trace, uint64_t *__restrict__ lde,
+                                                       Shape s, Twiddles tw) {
+  extern __shared__ uint64_t sh[];
+  const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT1, rs = n1 + 1;
+  const size_t n = size_t(1) << s.L, N = size_t(1) << (s.L + s.b);
+  const uint64_t *a = trace + size_t(blockIdx.y) * n;
+  uint64_t *y = lde + size_t(blockIdx.y) * N;
+  const int j2_0 = blockIdx.x << s.logT1;
+  const int total = T * n1;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e & (T - 1), j1 = e >> s.logT1;
+    sh[t * rs + j1] = a[size_t(j1) * n2 + j2_0 + t];
+  }
+  __syncthreads();
+  dif_rows(sh, T, s.L1, rs, tw.dft_inv);
+  const int shl = TW_LOG - s.L;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e & (T - 1), k1 = e >> s.logT1;
+    const uint32_t j2 = j2_0 + t;
+    uint64_t v = sh[t * rs + brev(k1, s.L1)];
+    const uint32_t ex = (uint32_t)((uint64_t(j2) * k1) & (n - 1));
+    if (ex) v = gl::mul(v, tw_pow(tw.inv_lo, tw.inv_hi, ex << shl));
+    y[size_t(k1) * n2 + j2] = v;
+  }
+}
+
+// Pass 2: tile = T consecutive residues k1 (rows of Y) of one column.
+__global__ void __launch_bounds__(THREADS) k_lde_pass2(const uint64_t *__restrict__ lde, uint64_t *__restrict__ z,
+                                                       int col0, Shape s, Twiddles tw,
+                                                       const uint64_t *__restrict__ twist,
+                                                       const uint64_t *__restrict__ scale) {
+  extern __shared__ uint64_t sh[];
+  const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT2, rs = n2 + 1, B = 1 << s.b;
+  const size_t N = size_t(1) << (s.L + s.b);
+  const int logN = s.L + s.b;
+  const uint64_t *y = lde + size_t(col0 + blockIdx.y) * N;
+  uint64_t *zc = z + size_t(blockIdx.y) * N;
+  const int k1_0 = blockIdx.x << s.logT2;
+  const int total = T * n2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e >> s.L2, j = e & (n2 - 1);
+    sh[t * rs + j] = y[size_t(k1_0 + t) * n2 + j];
+  }
+  __syncthreads();
+  dif_rows(sh, T, s.L2, rs, tw.dft_inv);
+  // keep n*c' scaled by n^-1 s^k1 in registers; position p holds natural index rev(p)
+  uint64_t keep[MAX_PER_THREAD];
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * THREADS;
+    if (e < total) {
+      const int t = e >> s.L2, p = e & (n2 - 1);
+      keep[m] = gl::mul(sh[t * rs + p], scale[k1_0 + t]);
+    }
+  }
+  __syncthreads();
+  const int shl = TW_LOG - logN;
+  for (int r = 0; r < B; r++) {
+    const uint64_t *twr = twist + size_t(r) * n2;
+#pragma unroll
+    for (int m = 0; m < MAX_PER_THREAD; m++) {
+      const int e = threadIdx.x + m * THREADS;
+      if (e < total) {
+        const int t = e >> s.L2, p = e & (n2 - 1);
+        sh[t * rs + p] = gl::mul(keep[m], twr[brev(p, s.L2)]);
+      }
+    }
+    __syncthreads();
+    dit_rows(sh, T, s.L2, rs, tw.dft_fwd);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e & (T - 1), m1 = e >> s.logT2;
+      const uint32_t k1 = k1_0 + t;
+      const uint32_t erow = r + (m1 << s.b);
+      uint64_t v = sh[t * rs + m1];
+      const uint32_t ex = (uint32_t)((uint64_t(k1) * erow) & (N - 1));
+      if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
+      zc[size_t(erow) * n1 + k1] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Pass 3: tile = T consecutive rows e of Z of one column.
+template <bool BITREV>
+__global__ void __launch_bounds__(THREADS) k_lde_pass3(const uint64_t *__restrict__ z, uint64_t *__restrict__ lde,
+                                                       int col0, Shape s, Twiddles tw) {
+  extern __shared__ uint64_t sh[];
+  const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT3, rs = n1 + 1, B = 1 << s.b;
+  const size_t N = size_t(1) << (s.L + s.b);
+  const uint64_t *zc = z + size_t(blockIdx.y) * N;
+  uint64_t *out = lde + size_t(col0 + blockIdx.y) * N;
+  const int e0 = blockIdx.x << s.logT3;
+  const int total = T * n1;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e >> s.L1, k1 = e & (n1 - 1);
+    sh[t * rs + k1] = zc[size_t(e0 + t) * n1 + k1];
+  }
+  __syncthreads();
+  dif_rows(sh, T, s.L1, rs, tw.dft_fwd);
+  if (!BITREV) {
+    const size_t stride = size_t(B) * n2;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e & (T - 1), m2 = e >> s.logT3;
+      out[size_t(e0 + t) + stride * m2] = sh[t * rs + brev(m2, s.L1)];
+    }
+  } else {
+    const int lr = s.L2 + s.b;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e >> s.L1, p = e & (n1 - 1);
+      out[size_t(brev(e0 + t, lr)) * n1 + p] = sh[t * rs + p];
+    }
+  }
+}
+
+int tile_log(int logM, int other_log) {
+  // T * M <= TILE_ELEMS, T <= 16, T <= size of the other dimension
+  int lt = DFT_LOG_MAX + 1 - logM;  // log2(8192 / M)
+  if (lt > 4) lt = 4;
+  if (lt < 0) lt = 0;
+  if (lt > other_log) lt = other_log;
+  return lt;
+}
+
+}  // namespace
+
+v3db_status build_twiddles(v3db_ctx *ctx) {
+  const size_t half = size_t(1) << TW_HALF;
+  std::vector<uint64_t> lo(half), hi(half), ilo(half), ihi(half), dfw(DFT_N / 2), dinv(DFT_N / 2);
+  const uint64_t w = gl::root_of_unity(TW_LOG), wi = gl::inv(w);
+  const uint64_t wstep = gl::pow(w, half), wistep = gl::pow(wi, half);
+  uint64_t a = 1, b = 1, c = 1, d = 1;
+  for (size_t i = 0; i < half; i++) {
+    lo[i] = a, hi[i] = b, ilo[i] = c, ihi[i] = d;
+    a = gl::mul(a, w), b = gl::mul(b, wstep), c = gl::mul(c, wi), d = gl::mul(d, wistep);
+  }
+  const uint64_t w4 = gl::root_of_unity(DFT_LOG_MAX), w4i = gl::inv(w4);
+  a = 1, c = 1;
+  for (int t = 0; t < DFT_N / 2; t++) {
+    dfw[t] = a, dinv[t] = c;
+    a = gl::mul(a, w4), c = gl::mul(c, w4i);
+  }
+  uint64_t *buf = nullptr;
+  const size_t total = 4 * half + DFT_N;
+  v3db_status st = ctx_alloc(ctx, (void **)&buf, total * 8, "twiddle tables");
+  if (st != V3DB_OK) return st;
+  ctx->tw.fwd_lo = buf;
+  ctx->tw.fwd_hi = buf + half;
+  ctx->tw.inv_lo = buf + 2 * half;
+  ctx->tw.inv_hi = buf + 3 * half;
+  ctx->tw.dft_fwd = buf + 4 * half;
+  ctx->tw.dft_inv = buf + 4 * half + DFT_N / 2;
+  std::vector<uint64_t> host(total);
+  std::copy(lo.begin(), lo.end(), host.begin());
+  std::copy(hi.begin(), hi.end(), host.begin() + half);
+  std::copy(ilo.begin(), ilo.end(), host.begin() + 2 * half);
+  std::copy(ihi.begin(), ihi.end(), host.begin() + 3 * half);
+  std::copy(dfw.begin(), dfw.end(), host.begin() + 4 * half);
+  std::copy(dinv.begin(), dinv.end(), host.begin() + 4 * half + DFT_N / 2);
+  return hip_check(hipMemcpy(buf, host.data(), total * 8, hipMemcpyHostToDevice), "upload twiddles");
+}
+
+void free_twiddles(v3db_ctx *ctx) {
+  if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, (4 * (size_t(1) << TW_HALF) + DFT_N) * 8);
+  ctx->tw = Twiddles{};
+  for (auto &kv : ctx->plans) {
+    const LdePlan &p = kv.second;
+    const size_t bytes = ((size_t(1) << (p.L2 + p.log_blowup)) + (size_t(1) << p.L1)) * 8;
+    ctx_free(ctx, p.d_twist, bytes);
+  }
+  ctx->plans.clear();
+}
+
+v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out) {
+  auto key = std::make_tuple(log_rows, log_blowup, shift);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = &it->second;
+    return V3DB_OK;
+  }
+  LdePlan p{};
+  p.log_rows = log_rows;
+  p.log_blowup = log_blowup;
+  p.shift = shift;
+  p.L1 = log_rows / 2;
+  p.L2 = log_rows - p.L1;
+  const size_t n1 = size_t(1) << p.L1, n2 = size_t(1) << p.L2, B = size_t(1) << log_blowup;
+  std::vector<uint64_t> host(B * n2 + n1);
+  // twist[r][j] = (s^n1 * w_{B n2}^r)^j
+  const uint64_t sn1 = gl::pow(shift, n1);
+  const uint64_t wb = gl::root_of_unity(p.L2 + log_blowup);
+  uint64_t wr = 1;
+  for (size_t r = 0; r < B; r++) {
+    const uint64_t base = gl::mul(sn1, wr);
+    uint64_t v = 1;
+    for (size_t j = 0; j < n2; j++) {
+      host[r * n2 + j] = v;
+      v = gl::mul(v, base);
+    }
+    wr = gl::mul(wr, wb);
+  }
+  // scale[k1] = n^-1 s^k1
+  uint64_t v = gl::inv(uint64_t(1) << log_rows);
+  for (size_t k = 0; k < n1; k++) {
+    host[B * n2 + k] = v;
+    v = gl::mul(v, shift);
+  }
+  uint64_t *buf = nullptr;
+  v3db_status st = ctx_alloc(ctx, (void **)&buf, host.size() * 8, "LDE plan tables");
+  if (st != V3DB_OK) return st;
+  st = hip_check(hipMemcpy(buf, host.data(), host.size() * 8, hipMemcpyHostToDevice), "upload plan");
+  if (st != V3DB_OK) {
+    ctx_free(ctx, buf, host.size() * 8);
+    return st;
+  }
+  p.d_twist = buf;
+  p.d_scale = buf + B * n2;
+  *out = &(ctx->plans[key] = p);
+  return V3DB_OK;
+}
+
+size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup) {
+  const uint32_t chunk = n_cols < LDE_CHUNK_COLS ? n_cols : LDE_CHUNK_COLS;
+  return size_t(chunk) * (size_t(8) << (log_rows + log_blowup));
+}
+
+v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, uint32_t log_rows,
+                        uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *lde,
+                        uint64_t *z, hipStream_t stream) {
+  const LdePlan *plan = nullptr;
+  v3db_status st = get_plan(ctx, log_rows, log_blowup, shift, &plan);
+  if (st != V3DB_OK) return st;
+  Shape s{};
+  s.L = (int)log_rows;
+  s.b = (int)log_blowup;
+  s.L1 = (int)plan->L1;
+  s.L2 = (int)plan->L2;
+  s.logT1 = tile_log(s.L1, s.L2);
+  s.logT2 = tile_log(s.L2, s.L1);
+  s.logT3 = tile_log(s.L1, s.L2 + s.b);
+  const size_t N = size_t(1) << (s.L + s.b);
+  (void)N;
+  // z holds Z for a chunk of columns at a time (lde_scratch_bytes)
+  const uint32_t chunk = n_cols < LDE_CHUNK_COLS ? n_cols : LDE_CHUNK_COLS;
+
+  const size_t sh1 = size_t(1 << s.logT1) * ((1 << s.L1) + 1) * 8;
+  const size_t sh2 = size_t(1 << s.logT2) * ((1 << s.L2) + 1) * 8;
+  const size_t sh3 = size_t(1 << s.logT3) * ((1 << s.L1) + 1) * 8;
+  static bool attr_done = false;
+  if (!attr_done) {
+    const int maxsh = 160 * 1024;
+    hipFuncSetAttribute((const void *)k_lde_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
+    hipFuncSetAttribute((const void *)k_lde_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
+    hipFuncSetAttribute((const void *)k_lde_pass3<false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
+    hipFuncSetAttribute((const void *)k_lde_pass3<true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
+    attr_done = true;
+  }
+  const Twiddles tw = ctx->tw;
+  dim3 g1((1u << s.L2) >> s.logT1, n_cols);
+  hipLaunchKernelGGL(k_lde_pass1, g1, dim3(THREADS), sh1, stream, trace, lde, s, tw);
+  for (uint32_t c0 = 0; c0 < n_cols; c0 += chunk) {
+    const uint32_t nc = (n_cols - c0) < chunk ? (n_cols - c0) : chunk;
+    dim3 g2((1u << s.L1) >> s.logT2, nc);
+    hipLaunchKernelGGL(k_lde_pass2, g2, dim3(THREADS), sh2, stream, lde, z, (int)c0, s, tw, plan->d_twist,
+                       plan->d_scale);
+    dim3 g3((1u << (s.L2 + s.b)) >> s.logT3, nc);
+    if (layout == V3DB_LAYOUT_BITREV)
+      hipLaunchKernelGGL(k_lde_pass3<true>, g3, dim3(THREADS), sh3, stream, z, lde, (int)c0, s, tw);
+    else
+      hipLaunchKernelGGL(k_lde_pass3<false>, g3, dim3(THREADS), sh3, stream, z, lde, (int)c0, s, tw);
+  }
+  return hip_check(hipGetLastError(), "LDE launch");
+}
+
+}  // namespace v3db

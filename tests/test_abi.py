@@ -1,0 +1,78 @@
+"""The C-ABI library: it loads, exports every entry point include/v3db.h
+declares, and its host-only logic (argument checks that need no device, constant
+derivation) behaves; no kernel runs here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "v3db.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(v3db_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def v3db():
+    import paper_2603_03065_amd as m
+    m.lib()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("v3db_lde", "v3db_poseidon_permute", "v3db_merkle_commit", "v3db_commit_batch",
+                     "v3db_ctx_create", "v3db_ctx_destroy", "v3db_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(v3db):
+    lib = v3db.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", v3db.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (v3db_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_library_constants_match_oracle(v3db, poseidon):
+    rc, circ, attempts = v3db.derive_poseidon_constants(poseidon.seed)
+    assert np.array_equal(rc, poseidon.rc)
+    assert np.array_equal(circ, poseidon.circ)
+    assert attempts == poseidon.mds_attempts
+
+
+def test_library_constants_other_seeds(v3db, oracle_mod):
+    for seed in (0, 1, 2**63 + 5):
+        o = oracle_mod.Poseidon(seed)
+        rc, circ, attempts = v3db.derive_poseidon_constants(seed)
+        assert np.array_equal(rc, o.rc) and np.array_equal(circ, o.circ) and attempts == o.mds_attempts
+
+
+def test_scratch_size_is_host_logic(v3db):
+    lib = v3db.lib()
+    J = v3db._Job
+    jobs = (J * 2)()
+    jobs[0] = J(None, 8, 12, 3, 0, 7, 0, None, None, None)
+    jobs[1] = J(None, 80, 10, 3, 2, 7, 0, None, None, None)
+    b = lib.v3db_commit_batch_scratch_bytes(jobs, 2)
+    # LDE 80 * 2^13 * 8 plus max(Z for 8 columns, tree (2^14 - 4) digests)
+    lde = 80 * (1 << 13) * 8
+    z = 8 * (1 << 13) * 8
+    tree = ((1 << 14) - 4) * 32
+    assert b == max(8 * (1 << 15) * 8 + max(8 * (1 << 15) * 8, ((1 << 16) - 1) * 32), lde + max(z, tree))
+
+
+def test_null_context_is_rejected_without_device(v3db):
+    lib = v3db.lib()
+    assert lib.v3db_lde(None, None, 1, 1, 3, 7, 0, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
+    assert lib.v3db_commit_batch(None, None, 0, None) == 1
+    assert lib.v3db_poseidon_permute(None, None, 0, None) == 1

@@ -1,0 +1,207 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle,
+bit-exact (all arithmetic is exact modular arithmetic: tolerance 0).
+
+Small shapes cover every tile size of the three LDE passes, ragged column counts
+(not multiples of the 8-element sponge rate), both layouts, all blowups and cap
+heights; full-size workloads are checked on sampled columns, rows and tree nodes
+the oracle can compute one by one, in the same launch configuration the
+benchmark times."""
+import numpy as np
+import pytest
+
+from paper_2603_03065_amd import inputs
+
+pytestmark = pytest.mark.gpu
+P = inputs.P
+
+
+@pytest.fixture(scope="module")
+def v3db():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2603_03065_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(v3db):
+    c = v3db.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(v3db, a):
+    return v3db.to_device(a)
+
+
+def _host(v3db, t):
+    import torch
+    torch.cuda.synchronize()
+    return v3db.to_host(t)
+
+
+# ----------------------------------------------------------------- Poseidon
+
+def test_constants_resident_match_oracle(ctx, poseidon):
+    rc, circ, att = ctx.poseidon_constants()
+    assert np.array_equal(rc, poseidon.rc) and np.array_equal(circ, poseidon.circ)
+
+
+@pytest.mark.parametrize("count", [1, 63, 64, 255, 257, 100_003])
+def test_permute_random_states(v3db, ctx, poseidon, count):
+    st = inputs.states(1000 + count, count)
+    d = _dev(v3db, st)
+    ctx.poseidon_permute(d)
+    assert np.array_equal(_host(v3db, d), poseidon.permute(st))
+
+
+def test_permute_edge_states(v3db, ctx, poseidon):
+    edge = [0, 1, 2, P - 1, P - 2, 2**32 - 1, 2**32, 2**63, P - 2**32]
+    rows = [[v] * 12 for v in edge] + [[edge[(i + j) % len(edge)] for j in range(12)] for i in range(len(edge))]
+    st = np.array(rows, dtype=np.uint64)
+    d = _dev(v3db, st)
+    ctx.poseidon_permute(d)
+    assert np.array_equal(_host(v3db, d), poseidon.permute(st))
+
+
+# ---------------------------------------------------------------------- LDE
+
+LDE_CASES = []
+for L in range(0, 15):
+    LDE_CASES.append((L, 3, 3, 0, 7))
+for L in (1, 5, 8, 11):
+    for b in (0, 1, 2, 4):
+        LDE_CASES.append((L, 2, b, 0, 7))
+for L in (0, 2, 6, 9, 12, 13):
+    LDE_CASES.append((L, 5, 3, 1, 7))
+LDE_CASES += [(10, 9, 3, 0, 3), (7, 1, 3, 1, P - 1), (4, 17, 3, 0, 12345678901)]
+
+
+@pytest.mark.parametrize("log_rows,n_cols,log_blowup,layout,shift", LDE_CASES)
+def test_lde_small(v3db, ctx, oracle_mod, log_rows, n_cols, log_blowup, layout, shift):
+    tr = inputs.trace(11, log_rows * 100 + log_blowup, n_cols, log_rows)
+    out = ctx.lde(_dev(v3db, tr), log_blowup, shift, layout)
+    assert np.array_equal(_host(v3db, out), oracle_mod.lde(tr, log_blowup, shift, layout))
+
+
+@pytest.mark.parametrize("log_rows,n_cols,layout", [(16, 3, 0), (17, 2, 1), (18, 2, 0), (20, 1, 1), (21, 1, 0)])
+def test_lde_large_full_columns(v3db, ctx, oracle_mod, log_rows, n_cols, layout):
+    # more columns than the pass-2 chunk would need if n_cols > 8; here the large sizes
+    # exercise the biggest LDS tiles (2^9..2^11-point sub-transforms)
+    tr = inputs.trace(12, log_rows, n_cols, log_rows)
+    out = ctx.lde(_dev(v3db, tr), 3, 7, layout)
+    assert np.array_equal(_host(v3db, out), oracle_mod.lde(tr, 3, 7, layout))
+
+
+def test_lde_many_columns_crosses_chunks(v3db, ctx, oracle_mod):
+    tr = inputs.trace(13, 0, 19, 9)   # 19 columns: chunks of 8, 8, 3
+    for layout in (0, 1):
+        out = ctx.lde(_dev(v3db, tr), 3, 7, layout)
+        assert np.array_equal(_host(v3db, out), oracle_mod.lde(tr, 3, 7, layout))
+
+
+# ------------------------------------------------------------------- Merkle
+
+@pytest.mark.parametrize("n_cols", [1, 4, 7, 8, 9, 16, 17, 80])
+@pytest.mark.parametrize("log_leaves,cap_height", [(0, 0), (1, 0), (1, 1), (5, 2), (10, 0), (10, 4), (13, 13)])
+def test_merkle_commit(v3db, ctx, poseidon, n_cols, log_leaves, cap_height):
+    import torch
+    mat = inputs.trace(14, n_cols * 64 + log_leaves, n_cols, log_leaves)
+    dm = _dev(v3db, mat)
+    tree = torch.empty(((2 << log_leaves) - (1 << cap_height), 4), dtype=torch.int64, device="cuda")
+    cap = ctx.merkle_commit(dm, cap_height, tree=tree)
+    ocap, otree = poseidon.merkle_commit(mat, cap_height, want_tree=True)
+    assert np.array_equal(_host(v3db, tree), otree)
+    assert np.array_equal(_host(v3db, cap), ocap)
+    cap2 = ctx.merkle_commit(dm, cap_height)           # tree in scratch
+    assert np.array_equal(_host(v3db, cap2), ocap)
+
+
+# ------------------------------------------------------------------- commit
+
+def _commit_one(v3db, ctx, tr, log_blowup, shift, layout, cap_height, want_all=True):
+    import torch
+    C, n = tr.shape
+    N = n << log_blowup
+    job = v3db.Job(trace=_dev(v3db, tr), log_blowup=log_blowup, cap_height=cap_height, shift=shift, layout=layout)
+    if want_all:
+        job.lde = torch.empty((C, N), dtype=torch.int64, device="cuda")
+        job.tree = torch.empty((2 * N - (1 << cap_height), 4), dtype=torch.int64, device="cuda")
+    ctx.commit(job)
+    return job
+
+
+def test_commit_small_workload_8x4096(v3db, ctx, oracle_mod, poseidon):
+    """8 columns x 2^12 rows, shift 7, blowup 8, each row hashed to a 4-element
+    digest, binary tree to a single root: whole LDE, tree and cap."""
+    tr = inputs.trace(1, 0, 8, 12)
+    job = _commit_one(v3db, ctx, tr, 3, 7, 0, 0)
+    ocap, olde, otree = poseidon.commit(tr, 3, 7, oracle_mod.NATURAL, 0, want_lde=True, want_tree=True)
+    assert np.array_equal(_host(v3db, job.lde), olde)
+    assert np.array_equal(_host(v3db, job.tree), otree)
+    assert np.array_equal(_host(v3db, job.cap), ocap)
+
+
+@pytest.mark.parametrize("C,L,b,layout,h", [(1, 0, 3, 0, 0), (3, 1, 3, 1, 2), (20, 6, 3, 0, 2), (9, 9, 2, 1, 5),
+                                              (135, 5, 3, 1, 4), (21, 10, 3, 0, 13)])
+def test_commit_ragged_shapes(v3db, ctx, oracle_mod, poseidon, C, L, b, layout, h):
+    tr = inputs.trace(15, C * 32 + L, C, L)
+    job = _commit_one(v3db, ctx, tr, b, 7, layout, h)
+    ocap, olde, otree = poseidon.commit(tr, b, 7, layout, h, want_lde=True, want_tree=True)
+    assert np.array_equal(_host(v3db, job.lde), olde)
+    assert np.array_equal(_host(v3db, job.tree), otree)
+    assert np.array_equal(_host(v3db, job.cap), ocap)
+
+
+def test_commit_scratch_buffers_give_same_cap(v3db, ctx, poseidon):
+    tr = inputs.trace(16, 0, 13, 9)
+    job = v3db.Job(trace=_dev(v3db, tr), log_blowup=3, cap_height=2)   # LDE and tree in scratch
+    ctx.commit(job)
+    ocap = poseidon.commit(tr, 3, 7, 0, 2)[0]
+    assert np.array_equal(_host(v3db, job.cap), ocap)
+
+
+def test_batch_equals_single(v3db, ctx, poseidon):
+    shapes = inputs.batch_shapes(6)
+    shapes = [(min(lr, 11), nc) for lr, nc in shapes]
+    trs = [inputs.trace(4, t, nc, lr) for t, (lr, nc) in enumerate(shapes)]
+    jobs = [v3db.Job(trace=_dev(v3db, tr), log_blowup=3, cap_height=2) for tr in trs]
+    caps = ctx.commit_batch(jobs)
+    for tr, cap in zip(trs, caps):
+        assert np.array_equal(_host(v3db, cap), poseidon.commit(tr, 3, 7, 0, 2)[0])
+
+
+def test_repeat_is_deterministic(v3db, ctx):
+    tr = inputs.trace(17, 0, 24, 12)
+    d = _dev(v3db, tr)
+    caps = []
+    for _ in range(20):
+        job = v3db.Job(trace=d, log_blowup=3, cap_height=3)
+        ctx.commit(job)
+        caps.append(_host(v3db, job.cap))
+    assert all(np.array_equal(caps[0], c) for c in caps)
+
+
+# ------------------------------------------------------------------- errors
+
+def test_invalid_arguments_raise(v3db, ctx):
+    import torch
+    tr = torch.zeros((2, 8), dtype=torch.int64, device="cuda")
+    with pytest.raises(v3db.V3dbError) as e:
+        ctx.lde(tr, 3, shift=0)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(v3db.V3dbError) as e:
+        ctx.lde(tr, 5, shift=7)
+    assert e.value.name == "UNSUPPORTED"
+    with pytest.raises(v3db.V3dbError) as e:
+        ctx.merkle_commit(tr, cap_height=4)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(v3db.V3dbError) as e:
+        v3db.Context(0, hbm_budget=1024)
+    assert e.value.name == "OUT_OF_MEMORY"
+
+
+def test_empty_permute_is_noop(v3db, ctx):
+    import torch
+    ctx.poseidon_permute(torch.zeros((0, 12), dtype=torch.int64, device="cuda"))

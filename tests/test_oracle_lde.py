@@ -80,3 +80,23 @@ def test_lde_rejects_invalid(oracle_mod):
         oracle_mod.lde(tr, 3, 0)
     with pytest.raises(ValueError):
         oracle_mod.lde(tr, 3, P)
+
+
+def test_eval_columns_matches_horner(oracle_mod):
+    rnd = random.Random(21)
+    cf = [[rnd.randrange(P) for _ in range(37)] for _ in range(3)]
+    xs = [0, 1, P - 1, rnd.randrange(P), rnd.randrange(P)]
+    out = oracle_mod.eval_columns(np.array(cf, dtype=np.uint64), xs)
+    for c in range(3):
+        assert [int(v) for v in out[c]] == [horner(cf[c], x) for x in xs]
+
+
+def test_interpolate_then_eval_reproduces_lde(oracle_mod):
+    rng = np.random.default_rng(22)
+    tr = rng.integers(0, P, size=(2, 64), dtype=np.uint64)
+    lde = oracle_mod.lde(tr, 3, 7)
+    cf = oracle_mod.interpolate(tr)
+    wN = root(9)
+    ks = [0, 3, 100, 511]
+    got = oracle_mod.eval_columns(cf, [7 * pow(wN, k, P) % P for k in ks])
+    assert np.array_equal(got, lde[:, ks])
