@@ -176,10 +176,13 @@ v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budge
     delete ctx;
     return set_error(V3DB_ERR_UNSUPPORTED, "ctx_create: no MDS circulant found in 1000 draws");
   }
-  v3db_status st = ctx_alloc(ctx, (void **)&ctx->d_pos, ROUNDS * WIDTH * 8, "Poseidon constants");
+  // the round constants followed by one row of zeros (the kernels add "next round's
+  // constants" inside every round's linear layer, the last one included)
+  uint64_t table[(ROUNDS + 1) * WIDTH] = {};
+  memcpy(table, ctx->pos.rc, sizeof(ctx->pos.rc));
+  v3db_status st = ctx_alloc(ctx, (void **)&ctx->d_pos, sizeof(table), "Poseidon constants");
   if (st == V3DB_OK)
-    st = hip_check(hipMemcpy(ctx->d_pos, ctx->pos.rc, ROUNDS * WIDTH * 8, hipMemcpyHostToDevice),
-                   "upload Poseidon constants");
+    st = hip_check(hipMemcpy(ctx->d_pos, table, sizeof(table), hipMemcpyHostToDevice), "upload Poseidon constants");
   if (st == V3DB_OK) st = build_twiddles(ctx);
   if (st != V3DB_OK) {
     v3db_ctx_destroy(ctx);
@@ -199,7 +202,7 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   for (auto &kv : ctx->scratch) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
   ctx->scratch.clear();
   free_twiddles(ctx);
-  ctx_free(ctx, ctx->d_pos, ROUNDS * WIDTH * 8);
+  ctx_free(ctx, ctx->d_pos, (ROUNDS + 1) * WIDTH * 8);
   delete ctx;
 }
 

@@ -33,12 +33,12 @@ GL_HD void mul_wide(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
 
 // Reduce hi*2^64 + lo (any 128-bit value) to a relaxed value in [0, 2^64).
 GL_HD uint64_t reduce128(uint64_t lo, uint64_t hi) {
-  uint64_t hh = hi >> 32, hl = hi & EPS;
-  uint64_t t0 = lo - hh;
-  if (lo < hh) t0 -= EPS;            // borrowed 2^64 = EPS (mod p); t0 >= 2^64 - 2^32 here
-  uint64_t t1 = (hl << 32) - hl;     // hl * (2^32 - 1)
-  uint64_t t2 = t0 + t1;
-  if (t2 < t1) t2 += EPS;            // carried 2^64; cannot carry again
+  const uint32_t hh = (uint32_t)(hi >> 32), hl = (uint32_t)hi;
+  uint64_t t0;
+  if (__builtin_sub_overflow(lo, (uint64_t)hh, &t0)) t0 -= EPS;  // borrowed 2^64 = EPS; t0 >= 2^64 - 2^32 here
+  const uint64_t t1 = (uint64_t)hl * EPS;                         // hl * (2^32 - 1)
+  uint64_t t2;
+  if (__builtin_add_overflow(t0, t1, &t2)) t2 += EPS;            // carried 2^64; cannot carry again
   return t2;
 }
 

@@ -29,7 +29,7 @@ struct PoseidonTables {
 struct Twiddles {
   uint64_t *fwd_lo, *fwd_hi;   // w^i and w^(2^13 i), w = w_{2^26}, i < 2^13
   uint64_t *inv_lo, *inv_hi;   // same for w^-1
-  uint64_t *dft_fwd, *dft_inv; // w_4096^t and w_4096^-t, t < 2048
+  uint64_t *dft_fwd, *dft_inv; // w_4096^t and w_4096^-t, t < 4096
 };
 
 // Per-shape LDE tables: see ntt.hip.

@@ -28,7 +28,7 @@ namespace v3db {
 
 namespace {
 
-constexpr int THREADS = 256;
+constexpr int THREADS = 512;
 constexpr int DFT_N = 1 << DFT_LOG_MAX;  // 4096
 constexpr int TILE_ELEMS = 8192;         // T * M per tile
 constexpr int MAX_PER_THREAD = TILE_ELEMS / THREADS;
@@ -43,48 +43,139 @@ __device__ __forceinline__ uint64_t tw_pow(const uint64_t *__restrict__ lo, cons
   return gl::mul(hi[e >> TW_HALF], lo[e & ((1u << TW_HALF) - 1)]);
 }
 
-// Radix-2 decimation in frequency along each of T rows of length 2^logM (row
-// stride rs) in LDS: natural order in, bit-reversed order out. tw = w_4096^t.
-__device__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
-  if (logM == 0) return;
-  const int half = 1 << (logM - 1);
-  const int nb = T * half;
-  for (int logh = logM - 1; logh >= 0; --logh) {
-    const int h = 1 << logh;
-    const int tws = DFT_N >> (logh + 1);
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const int t = b >> (logM - 1);
-      const int q = b & (half - 1);
-      const int i = q & (h - 1);
-      const int i0 = t * rs + ((q >> logh) << (logh + 1)) + i;
-      const uint64_t u = sh[i0], v = sh[i0 + h];
-      sh[i0] = gl::add(u, v);
-      const uint64_t d = gl::sub(u, v);
-      sh[i0 + h] = i ? gl::mul(d, tw[i * tws]) : d;
+// Powers of w_8 = 7^((p-1)/8) (forward) and of its inverse; all are +-2^(24 k),
+// so with these compile-time operands the products need only half the partial
+// products.
+__device__ __forceinline__ uint64_t w8(int k, bool inv) {
+  constexpr uint64_t F[4] = {1ull, 18446744069397807105ull, 281474976710656ull, 18446742969902956801ull};
+  constexpr uint64_t I[4] = {1ull, 1099511627520ull, 18446462594437873665ull, 16777216ull};
+  return inv ? I[k] : F[k];
+}
+
+// Size-R transform in registers (R = 2, 4, 8) by radix-2 stages.
+// dif: natural order in, bit-reversed order out. dit: bit-reversed in, natural out.
+template <int R, bool INV>
+__device__ __forceinline__ void reg_dif(uint64_t v[R]) {
+#pragma unroll
+  for (int h = R / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * h)
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        const uint64_t u = v[b + i], w = v[b + i + h];
+        v[b + i] = gl::add(u, w);
+        const uint64_t d = gl::sub(u, w);
+        v[b + i + h] = i ? gl::mul(d, w8(i * (8 / (2 * h)), INV)) : d;
+      }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void reg_dit(uint64_t v[R]) {
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * h)
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        const uint64_t u = v[b + i];
+        uint64_t w = v[b + i + h];
+        if (i) w = gl::mul(w, w8(i * (8 / (2 * h)), INV));
+        v[b + i] = gl::add(u, w);
+        v[b + i + h] = gl::sub(u, w);
+      }
+}
+
+template <int R>
+__device__ __forceinline__ int brev_r(int j) {
+  return R == 8 ? ((j & 1) << 2 | (j & 2) | (j >> 2)) : R == 4 ? ((j & 1) << 1 | (j >> 1)) : j;
+}
+
+// One radix-R pass of a decimation-in-frequency transform over T rows of
+// 2^logM words in LDS (row stride rs): sub-blocks of 2^logS words, each
+// butterfly takes the R words i + j*2^logS/R, transforms them, and multiplies
+// output slot j (frequency bitrev(j)) by w_S^(i * bitrev(j)). tw = w_4096^t.
+template <int R, bool INV>
+__device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, int logS,
+                                         const uint64_t *__restrict__ tw) {
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int logStride = logS - LR;
+  const int per_row = 1 << (logM - LR);
+  const int nb = T * per_row;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int t = b >> (logM - LR);
+    const int q = b & (per_row - 1);
+    const int i = q & ((1 << logStride) - 1);
+    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
+    reg_dif<R, INV>(v);
+    if (i) {
+#pragma unroll
+      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
     }
+#pragma unroll
+    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
+  }
+}
+
+// One radix-R pass of a decimation-in-time transform: combines R transformed
+// sub-blocks of 2^logS/R words into one of 2^logS words.
+template <int R, bool INV>
+__device__ __forceinline__ void dit_pass(uint64_t *sh, int T, int logM, int rs, int logS,
+                                         const uint64_t *__restrict__ tw) {
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int logStride = logS - LR;
+  const int per_row = 1 << (logM - LR);
+  const int nb = T * per_row;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int t = b >> (logM - LR);
+    const int q = b & (per_row - 1);
+    const int i = q & ((1 << logStride) - 1);
+    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
+    if (i) {
+#pragma unroll
+      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
+    }
+    reg_dit<R, INV>(v);
+#pragma unroll
+    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
+  }
+}
+
+// Whole transforms over the rows: radix-8 passes, then one radix-4 or radix-2
+// pass for the remaining bits. Each pass ends with a barrier.
+template <bool INV>
+__device__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  int logS = logM;
+  for (; logS >= 3; logS -= 3) {
+    dif_pass<8, INV>(sh, T, logM, rs, logS, tw);
+    __syncthreads();
+  }
+  if (logS == 2) {
+    dif_pass<4, INV>(sh, T, logM, rs, 2, tw);
+    __syncthreads();
+  } else if (logS == 1) {
+    dif_pass<2, INV>(sh, T, logM, rs, 1, tw);
     __syncthreads();
   }
 }
 
-// Radix-2 decimation in time: bit-reversed order in, natural order out.
+template <bool INV>
 __device__ void dit_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
-  if (logM == 0) return;
-  const int half = 1 << (logM - 1);
-  const int nb = T * half;
-  for (int logh = 0; logh < logM; ++logh) {
-    const int h = 1 << logh;
-    const int tws = DFT_N >> (logh + 1);
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const int t = b >> (logM - 1);
-      const int q = b & (half - 1);
-      const int i = q & (h - 1);
-      const int i0 = t * rs + ((q >> logh) << (logh + 1)) + i;
-      const uint64_t u = sh[i0];
-      uint64_t v = sh[i0 + h];
-      if (i) v = gl::mul(v, tw[i * tws]);
-      sh[i0] = gl::add(u, v);
-      sh[i0 + h] = gl::sub(u, v);
-    }
+  int logS = logM % 3;
+  if (logS == 2) {
+    dit_pass<4, INV>(sh, T, logM, rs, 2, tw);
+    __syncthreads();
+  } else if (logS == 1) {
+    dit_pass<2, INV>(sh, T, logM, rs, 1, tw);
+    __syncthreads();
+  }
+  for (logS += 3; logS <= logM; logS += 3) {
+    dit_pass<8, INV>(sh, T, logM, rs, logS, tw);
     __syncthreads();
   }
 }
@@ -109,7 +200,7 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass1(const uint64_t *__restric
     sh[t * rs + j1] = a[size_t(j1) * n2 + j2_0 + t];
   }
   __syncthreads();
-  dif_rows(sh, T, s.L1, rs, tw.dft_inv);
+  dif_rows<true>(sh, T, s.L1, rs, tw.dft_inv);
   const int shl = TW_LOG - s.L;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = e & (T - 1), k1 = e >> s.logT1;
@@ -139,7 +230,7 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass2(const uint64_t *__restric
     sh[t * rs + j] = y[size_t(k1_0 + t) * n2 + j];
   }
   __syncthreads();
-  dif_rows(sh, T, s.L2, rs, tw.dft_inv);
+  dif_rows<true>(sh, T, s.L2, rs, tw.dft_inv);
   // keep n*c' scaled by n^-1 s^k1 in registers; position p holds natural index rev(p)
   uint64_t keep[MAX_PER_THREAD];
 #pragma unroll
@@ -163,7 +254,7 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass2(const uint64_t *__restric
       }
     }
     __syncthreads();
-    dit_rows(sh, T, s.L2, rs, tw.dft_fwd);
+    dit_rows<false>(sh, T, s.L2, rs, tw.dft_fwd);
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e & (T - 1), m1 = e >> s.logT2;
       const uint32_t k1 = k1_0 + t;
@@ -193,7 +284,7 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass3(const uint64_t *__restric
     sh[t * rs + k1] = zc[size_t(e0 + t) * n1 + k1];
   }
   __syncthreads();
-  dif_rows(sh, T, s.L1, rs, tw.dft_fwd);
+  dif_rows<false>(sh, T, s.L1, rs, tw.dft_fwd);
   if (!BITREV) {
     const size_t stride = size_t(B) * n2;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -222,7 +313,7 @@ int tile_log(int logM, int other_log) {
 
 v3db_status build_twiddles(v3db_ctx *ctx) {
   const size_t half = size_t(1) << TW_HALF;
-  std::vector<uint64_t> lo(half), hi(half), ilo(half), ihi(half), dfw(DFT_N / 2), dinv(DFT_N / 2);
+  std::vector<uint64_t> lo(half), hi(half), ilo(half), ihi(half), dfw(DFT_N), dinv(DFT_N);
   const uint64_t w = gl::root_of_unity(TW_LOG), wi = gl::inv(w);
   const uint64_t wstep = gl::pow(w, half), wistep = gl::pow(wi, half);
   uint64_t a = 1, b = 1, c = 1, d = 1;
@@ -232,12 +323,12 @@ v3db_status build_twiddles(v3db_ctx *ctx) {
   }
   const uint64_t w4 = gl::root_of_unity(DFT_LOG_MAX), w4i = gl::inv(w4);
   a = 1, c = 1;
-  for (int t = 0; t < DFT_N / 2; t++) {
+  for (int t = 0; t < DFT_N; t++) {
     dfw[t] = a, dinv[t] = c;
     a = gl::mul(a, w4), c = gl::mul(c, w4i);
   }
   uint64_t *buf = nullptr;
-  const size_t total = 4 * half + DFT_N;
+  const size_t total = 4 * half + 2 * DFT_N;
   v3db_status st = ctx_alloc(ctx, (void **)&buf, total * 8, "twiddle tables");
   if (st != V3DB_OK) return st;
   ctx->tw.fwd_lo = buf;
@@ -245,19 +336,19 @@ v3db_status build_twiddles(v3db_ctx *ctx) {
   ctx->tw.inv_lo = buf + 2 * half;
   ctx->tw.inv_hi = buf + 3 * half;
   ctx->tw.dft_fwd = buf + 4 * half;
-  ctx->tw.dft_inv = buf + 4 * half + DFT_N / 2;
+  ctx->tw.dft_inv = buf + 4 * half + DFT_N;
   std::vector<uint64_t> host(total);
   std::copy(lo.begin(), lo.end(), host.begin());
   std::copy(hi.begin(), hi.end(), host.begin() + half);
   std::copy(ilo.begin(), ilo.end(), host.begin() + 2 * half);
   std::copy(ihi.begin(), ihi.end(), host.begin() + 3 * half);
   std::copy(dfw.begin(), dfw.end(), host.begin() + 4 * half);
-  std::copy(dinv.begin(), dinv.end(), host.begin() + 4 * half + DFT_N / 2);
+  std::copy(dinv.begin(), dinv.end(), host.begin() + 4 * half + DFT_N);
   return hip_check(hipMemcpy(buf, host.data(), total * 8, hipMemcpyHostToDevice), "upload twiddles");
 }
 
 void free_twiddles(v3db_ctx *ctx) {
-  if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, (4 * (size_t(1) << TW_HALF) + DFT_N) * 8);
+  if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, (4 * (size_t(1) << TW_HALF) + 2 * DFT_N) * 8);
   ctx->tw = Twiddles{};
   for (auto &kv : ctx->plans) {
     const LdePlan &p = kv.second;

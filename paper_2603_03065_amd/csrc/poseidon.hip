@@ -30,63 +30,86 @@ __device__ __forceinline__ uint64_t sbox(uint64_t x) {
   return gl::mul_r(x3, x4);
 }
 
-// lo + hi * 2^32 with lo, hi < 2^44, reduced to [0, 2^64).
+// lo + hi * 2^32 for lo, hi < 2^46, to a relaxed value: with hi = hh*2^32 + hl,
+// the sum is lo + hh*2^64 + hl*2^32 = (hh*(2^32-1) + lo) + hl*2^32 (mod p); the
+// first part is one multiply-add below 2^47, the second adds hl to its high word
+// and a carry out of bit 64 is worth 2^32 - 1 again.
 __device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
-  const uint64_t s = lo + (hi << 32);
-  const uint32_t k = (uint32_t)(hi >> 32) + (s < lo ? 1u : 0u);  // multiples of 2^64
-  const uint64_t kk = ((uint64_t)k << 32) - k;                    // k * (2^64 mod p)
-  uint64_t r = s + kk;
-  if (r < kk) r += gl::EPS;
+  const uint64_t t = (uint64_t)(uint32_t)(hi >> 32) * gl::EPS + lo;
+  const uint32_t th = (uint32_t)(t >> 32);
+  const uint32_t rh = th + (uint32_t)hi;
+  uint64_t r = ((uint64_t)rh << 32) | (uint32_t)t;
+  if (rh < th) r += gl::EPS;
   return r;
 }
 
-__device__ __forceinline__ void mds(uint64_t s[WIDTH], const Circ &c) {
-  uint64_t out[WIDTH];
+// state <- M * state + rc_next. The next round's constants enter as the initial
+// values of the two accumulators (their low and high 32-bit halves), so the
+// constant addition costs nothing. All sums stay below 2^44.
+__device__ __forceinline__ void mds_ark(uint64_t s[WIDTH], const uint32_t a[WIDTH],
+                                        const uint64_t *__restrict__ rc_next) {
+  uint32_t lo[WIDTH], hi[WIDTH];
 #pragma unroll
-  for (int i = 0; i < WIDTH; i++) {
-    uint64_t lo = 0, hi = 0;
-#pragma unroll
-    for (int j = 0; j < WIDTH; j++) {
-      const uint32_t a = c.a[(j - i + WIDTH) % WIDTH];
-      lo += (uint64_t)a * (uint32_t)s[j];
-      hi += (uint64_t)a * (uint32_t)(s[j] >> 32);
-    }
-    out[i] = fold(lo, hi);
+  for (int j = 0; j < WIDTH; j++) {
+    lo[j] = (uint32_t)s[j];
+    hi[j] = (uint32_t)(s[j] >> 32);
   }
 #pragma unroll
-  for (int i = 0; i < WIDTH; i++) s[i] = out[i];
-}
-
-__device__ __forceinline__ void full_round(uint64_t s[WIDTH], const uint64_t *__restrict__ rc, const Circ &c) {
+  for (int i = 0; i < WIDTH; i++) {
+    const uint64_t rc = rc_next[i];
+    uint64_t al = (uint32_t)rc, ah = rc >> 32;
 #pragma unroll
-  for (int i = 0; i < WIDTH; i++) s[i] = sbox(gl::add_r(s[i], rc[i]));
-  mds(s, c);
+    for (int j = 0; j < WIDTH; j++) {
+      const uint32_t c = a[(j - i + WIDTH) % WIDTH];
+      al += (uint64_t)c * lo[j];
+      ah += (uint64_t)c * hi[j];
+    }
+    s[i] = fold(al, ah);
+  }
 }
 
-__device__ __forceinline__ void partial_round(uint64_t s[WIDTH], const uint64_t *__restrict__ rc, const Circ &c) {
-  s[0] = sbox(gl::add_r(s[0], rc[0]));
+// The matrix entries as per-lane registers: with the multiplier in a VGPR, the
+// accumulator's initial value (a round constant in SGPRs) can be the
+// multiply-add's scalar operand.
+__device__ __forceinline__ void circ_to_vgprs(const Circ &c, uint32_t a[WIDTH]) {
 #pragma unroll
-  for (int i = 1; i < WIDTH; i++) s[i] = gl::add_r(s[i], rc[i]);
-  mds(s, c);
+  for (int i = 0; i < WIDTH; i++) asm volatile("v_mov_b32 %0, %1" : "=v"(a[i]) : "s"(c.a[i]));
 }
 
-__device__ __forceinline__ void permute(uint64_t s[WIDTH], const uint64_t *__restrict__ rc, const Circ &c) {
+// rc: 31 rows of 12 (the 30 rounds' constants, then a row of zeros so the last
+// round's linear layer can take "next constants" like every other round).
+__device__ __forceinline__ void permute(uint64_t s[WIDTH], const uint64_t *__restrict__ rc, const uint32_t a[WIDTH]) {
+#pragma unroll
+  for (int i = 0; i < WIDTH; i++) s[i] = gl::add_r(s[i], rc[i]);
 #pragma unroll 1
-  for (int r = 0; r < FULL_HALF; r++) full_round(s, rc + r * WIDTH, c);
+  for (int r = 0; r < FULL_HALF; r++) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
 #pragma unroll 1
-  for (int r = FULL_HALF; r < ROUNDS - FULL_HALF; r++) partial_round(s, rc + r * WIDTH, c);
+  for (int r = FULL_HALF; r < ROUNDS - FULL_HALF; r++) {
+    s[0] = sbox(s[0]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
 #pragma unroll 1
-  for (int r = ROUNDS - FULL_HALF; r < ROUNDS; r++) full_round(s, rc + r * WIDTH, c);
+  for (int r = ROUNDS - FULL_HALF; r < ROUNDS; r++) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
 }
 
 __global__ void __launch_bounds__(THREADS) k_permute(uint64_t *__restrict__ states, size_t count,
                                                      const uint64_t *__restrict__ rc, Circ c) {
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= count) return;
+  uint32_t a[WIDTH];
+  circ_to_vgprs(c, a);
   uint64_t s[WIDTH];
 #pragma unroll
   for (int i = 0; i < WIDTH; i++) s[i] = states[k * WIDTH + i];
-  permute(s, rc, c);
+  permute(s, rc, a);
 #pragma unroll
   for (int i = 0; i < WIDTH; i++) states[k * WIDTH + i] = gl::canon(s[i]);
 }
@@ -98,6 +121,8 @@ __global__ void __launch_bounds__(THREADS) k_leaf_hash(const uint64_t *__restric
                                                        const uint64_t *__restrict__ rc, Circ c) {
   const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n_rows) return;
+  uint32_t a[WIDTH];
+  circ_to_vgprs(c, a);
   uint64_t s[WIDTH];
 #pragma unroll
   for (int i = 0; i < WIDTH; i++) s[i] = 0;
@@ -107,7 +132,7 @@ __global__ void __launch_bounds__(THREADS) k_leaf_hash(const uint64_t *__restric
 #pragma unroll
     for (int i = 0; i < RATE; i++)
       if (i < (int)len) s[i] = base[uint64_t(i) * n_rows];
-    permute(s, rc, c);
+    permute(s, rc, a);
   }
   uint64_t *d = dig + k * DIGEST;
 #pragma unroll
@@ -120,13 +145,15 @@ __global__ void __launch_bounds__(THREADS) k_merkle_level(const uint64_t *__rest
                                                           const uint64_t *__restrict__ rc, Circ c) {
   const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= count) return;
+  uint32_t a[WIDTH];
+  circ_to_vgprs(c, a);
   uint64_t s[WIDTH];
   const uint64_t *src = below + k * (2 * DIGEST);
 #pragma unroll
   for (int i = 0; i < 2 * DIGEST; i++) s[i] = src[i];
 #pragma unroll
   for (int i = 2 * DIGEST; i < WIDTH; i++) s[i] = 0;
-  permute(s, rc, c);
+  permute(s, rc, a);
   uint64_t *d = above + k * DIGEST;
 #pragma unroll
   for (int i = 0; i < DIGEST; i++) d[i] = gl::canon(s[i]);
