@@ -7,10 +7,10 @@
 //   pass 1  (interpolation, first half)   j = j1*n2 + j2, k = k1 + n1*k2
 //           Y[k1][j2] = w_n^(-j2 k1) * sum_j1 a[j1 n2 + j2] w_n1^(-j1 k1)
 //   pass 2  per residue k1: c'[k2] = sum_j2 Y[k1][j2] w_n2^(-j2 k2)   (= n c[k1 + n1 k2])
-//           then, for each coset row e = r + B*m1 (r < B, m1 < n2), a blowup-B
-//           extension of that residue sequence with shift s^n1:
-//           Z[e][k1] = n^-1 s^k1 w_N^(k1 e) * sum_k2 c'[k2] (s^n1 w_(B n2)^r)^k2 w_n2^(k2 m1)
-//   pass 3  per row e: LDE[e + B n2 m2] = sum_k1 Z[e][k1] w_n1^(k1 m2)
+//           then a blowup-B extension of that residue sequence with shift s^n1,
+//           for every e < W = B*n2 (e = r + B*m1: coset r, point m1):
+//           Z[k1][e] = n^-1 s^k1 w_N^(k1 e) * sum_k2 c'[k2] (s^n1)^k2 w_W^(k2 e)
+//   pass 3  per column e of Z: LDE[e + W m2] = sum_k1 Z[k1][e] w_n1^(k1 m2)
 //
 // (LDE[e + B n2 m2] = sum_k1 w_n1^(k1 m2) s^k1 w_N^(k1 e) sum_k2 c[k1+n1 k2]
 //  (s^n1)^k2 w_(B n2)^(k2 e) follows from j = k1 + n1 k2 and k = e + B n2 m2.)
@@ -20,8 +20,9 @@
 // for natural -> bit-reversed, decimation-in-time for bit-reversed -> natural),
 // and applies the twiddles on the way out. Pass 1 writes Y into the first n
 // entries of the output column (free until pass 3); pass 2 writes Z (B*n per
-// column) to scratch, a chunk of columns at a time; pass 3 writes the output in
-// natural order (runs of T) or bit-reversed order (contiguous rows).
+// column, rows of W contiguous words) to scratch, a chunk of columns at a time;
+// pass 3 reads runs of T words of Z and writes the output in natural order
+// (runs of T) or bit-reversed order (contiguous rows).
 #include "internal.h"
 
 namespace v3db {
@@ -148,9 +149,11 @@ __device__ __forceinline__ void dit_pass(uint64_t *sh, int T, int logM, int rs, 
 
 // Whole transforms over the rows: radix-8 passes, then one radix-4 or radix-2
 // pass for the remaining bits. Each pass ends with a barrier.
+// Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
+// were done another way).
 template <bool INV>
-__device__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
-  int logS = logM;
+__device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ tw) {
+  int logS = logS0;
   for (; logS >= 3; logS -= 3) {
     dif_pass<8, INV>(sh, T, logM, rs, logS, tw);
     __syncthreads();
@@ -162,6 +165,11 @@ __device__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *
     dif_pass<2, INV>(sh, T, logM, rs, 1, tw);
     __syncthreads();
   }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  dif_rows_from<INV>(sh, T, logM, logM, rs, tw);
 }
 
 template <bool INV>
@@ -212,59 +220,61 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass1(const uint64_t *__restric
   }
 }
 
-// Pass 2: tile = T consecutive residues k1 (rows of Y) of one column.
+// Pass 2: tile = T consecutive residues k1 (rows of Y) of one column; W = B*n2.
+// Row k1 of Y is transformed back (giving n*c[k1 + n1*k2] in bit-reversed
+// positions), scaled by n^-1 s^k1 and expanded to the W-point zero-padded
+// transform: its first radix-B decimation-in-frequency pass has a single
+// nonzero input per butterfly, so output slot j of butterfly i is the input
+// times the twist (s^n1 w_W^r)^i, r = bitrev(j). The remaining passes run on the
+// B cosets together; row k1 of Z gets Z[k1][e] = w_N^(k1 e) * (result at e).
 __global__ void __launch_bounds__(THREADS) k_lde_pass2(const uint64_t *__restrict__ lde, uint64_t *__restrict__ z,
                                                        int col0, Shape s, Twiddles tw,
                                                        const uint64_t *__restrict__ twist,
                                                        const uint64_t *__restrict__ scale) {
   extern __shared__ uint64_t sh[];
-  const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT2, rs = n2 + 1, B = 1 << s.b;
+  const int n2 = 1 << s.L2, T = 1 << s.logT2, B = 1 << s.b;
+  const int LW = s.L2 + s.b, W = 1 << LW, rs = W + 1;
   const size_t N = size_t(1) << (s.L + s.b);
   const int logN = s.L + s.b;
   const uint64_t *y = lde + size_t(col0 + blockIdx.y) * N;
   uint64_t *zc = z + size_t(blockIdx.y) * N;
   const int k1_0 = blockIdx.x << s.logT2;
-  const int total = T * n2;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+  const int total_in = T << s.L2;
+  for (int e = threadIdx.x; e < total_in; e += blockDim.x) {
     const int t = e >> s.L2, j = e & (n2 - 1);
     sh[t * rs + j] = y[size_t(k1_0 + t) * n2 + j];
   }
   __syncthreads();
   dif_rows<true>(sh, T, s.L2, rs, tw.dft_inv);
-  // keep n*c' scaled by n^-1 s^k1 in registers; position p holds natural index rev(p)
-  uint64_t keep[MAX_PER_THREAD];
+  uint64_t c[MAX_PER_THREAD];
 #pragma unroll
   for (int m = 0; m < MAX_PER_THREAD; m++) {
     const int e = threadIdx.x + m * THREADS;
-    if (e < total) {
-      const int t = e >> s.L2, p = e & (n2 - 1);
-      keep[m] = gl::mul(sh[t * rs + p], scale[k1_0 + t]);
+    if (e < total_in) {
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      c[m] = gl::mul(sh[t * rs + brev(i, s.L2)], scale[k1_0 + t]);
     }
   }
   __syncthreads();
-  const int shl = TW_LOG - logN;
-  for (int r = 0; r < B; r++) {
-    const uint64_t *twr = twist + size_t(r) * n2;
 #pragma unroll
-    for (int m = 0; m < MAX_PER_THREAD; m++) {
-      const int e = threadIdx.x + m * THREADS;
-      if (e < total) {
-        const int t = e >> s.L2, p = e & (n2 - 1);
-        sh[t * rs + p] = gl::mul(keep[m], twr[brev(p, s.L2)]);
-      }
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * THREADS;
+    if (e < total_in) {
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      for (int j = 0; j < B; j++) sh[t * rs + i + (j << s.L2)] = gl::mul(c[m], twist[(brev(j, s.b) << s.L2) + i]);
     }
-    __syncthreads();
-    dit_rows<false>(sh, T, s.L2, rs, tw.dft_fwd);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int t = e & (T - 1), m1 = e >> s.logT2;
-      const uint32_t k1 = k1_0 + t;
-      const uint32_t erow = r + (m1 << s.b);
-      uint64_t v = sh[t * rs + m1];
-      const uint32_t ex = (uint32_t)((uint64_t(k1) * erow) & (N - 1));
-      if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
-      zc[size_t(erow) * n1 + k1] = v;
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.dft_fwd);
+  const int total_out = T << LW;
+  const int shl = TW_LOG - logN;
+  for (int e = threadIdx.x; e < total_out; e += blockDim.x) {
+    const int t = e >> LW, f = e & (W - 1);
+    const uint32_t k1 = k1_0 + t;
+    uint64_t v = sh[t * rs + brev(f, LW)];
+    const uint32_t ex = (uint32_t)((uint64_t(k1) * f) & (N - 1));
+    if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
+    zc[(size_t(k1) << LW) + f] = v;
   }
 }
 
@@ -279,9 +289,10 @@ __global__ void __launch_bounds__(THREADS) k_lde_pass3(const uint64_t *__restric
   uint64_t *out = lde + size_t(col0 + blockIdx.y) * N;
   const int e0 = blockIdx.x << s.logT3;
   const int total = T * n1;
+  const int LW = s.L2 + s.b;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int t = e >> s.L1, k1 = e & (n1 - 1);
-    sh[t * rs + k1] = zc[size_t(e0 + t) * n1 + k1];
+    const int t = e & (T - 1), k1 = e >> s.logT3;
+    sh[t * rs + k1] = zc[(size_t(k1) << LW) + e0 + t];
   }
   __syncthreads();
   dif_rows<false>(sh, T, s.L1, rs, tw.dft_fwd);
@@ -369,8 +380,10 @@ v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint
   p.log_rows = log_rows;
   p.log_blowup = log_blowup;
   p.shift = shift;
-  p.L1 = log_rows / 2;
-  p.L2 = log_rows - p.L1;
+  // n2 = 2^L2 with B*n2 <= 2^14 (pass 2 holds B*n2 words per residue in LDS), n1 <= 2^12
+  p.L2 = log_rows / 2;
+  if (p.L2 + log_blowup > 14) p.L2 = 14 - log_blowup;
+  p.L1 = log_rows - p.L2;
   const size_t n1 = size_t(1) << p.L1, n2 = size_t(1) << p.L2, B = size_t(1) << log_blowup;
   std::vector<uint64_t> host(B * n2 + n1);
   // twist[r][j] = (s^n1 * w_{B n2}^r)^j
@@ -423,7 +436,7 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
   s.L1 = (int)plan->L1;
   s.L2 = (int)plan->L2;
   s.logT1 = tile_log(s.L1, s.L2);
-  s.logT2 = tile_log(s.L2, s.L1);
+  s.logT2 = tile_log(s.L2 + s.b, s.L1);
   s.logT3 = tile_log(s.L1, s.L2 + s.b);
   const size_t N = size_t(1) << (s.L + s.b);
   (void)N;
@@ -431,7 +444,7 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
   const uint32_t chunk = n_cols < LDE_CHUNK_COLS ? n_cols : LDE_CHUNK_COLS;
 
   const size_t sh1 = size_t(1 << s.logT1) * ((1 << s.L1) + 1) * 8;
-  const size_t sh2 = size_t(1 << s.logT2) * ((1 << s.L2) + 1) * 8;
+  const size_t sh2 = size_t(1 << s.logT2) * ((1 << (s.L2 + s.b)) + 1) * 8;
   const size_t sh3 = size_t(1 << s.logT3) * ((1 << s.L1) + 1) * 8;
   static bool attr_done = false;
   if (!attr_done) {
