@@ -35,6 +35,7 @@ WORKLOADS = {
     "commit-8x2^12": ("8 cols x 2^12 rows, blowup 8 -> 2^15 rows, one permutation per row, cap height 0",
                       8, 12, 3, 0, 0, 1),
 }
+BATCH_WORKLOAD = "commit-batch-64"   # 64 traces: log rows U{10..18}, cols U[20,135], blowup 8, cap 2
 DEFAULT_WORKLOAD = "commit-80x2^18"
 
 # Peaks of one MI355X (gfx950): 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + [BATCH_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
                     help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
@@ -81,12 +82,76 @@ def cpu_baseline(n_cols, log_blowup, cap_height, layout, log_rows):
     }
 
 
+def batch_main(args):
+    """64 traces of mixed shapes committed by one v3db_commit_batch call (batched
+    phase launches replayed from a HIP graph), against the same jobs committed
+    one trace at a time (one launch sequence per trace)."""
+    import numpy as np
+    import torch
+
+    import paper_2603_03065_amd as v3db
+    from paper_2603_03065_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shapes = inputs.batch_shapes(64)
+    ctx = v3db.Context(0)
+    jobs = []
+    elems = 0
+    for t, (L, C) in enumerate(shapes):
+        N = 1 << (L + 3)
+        jobs.append(v3db.Job(trace=v3db.to_device(inputs.trace(4, t, C, L), dev), log_blowup=3, cap_height=2,
+                             lde=torch.empty((C, N), dtype=torch.int64, device=dev),
+                             tree=torch.empty((2 * N - 4, 4), dtype=torch.int64, device=dev)))
+        elems += C * N
+    stream = torch.cuda.current_stream(dev)
+
+    def run(batching, steps, warmup):
+        ctx.set_batching(batching)
+        for _ in range(warmup):
+            ctx.commit_batch(jobs, stream)
+        torch.cuda.synchronize()
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        marks[0].record(stream)
+        for k in range(steps):
+            ctx.commit_batch(jobs, stream)
+            marks[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(steps)])
+
+    wall_b, ms_b = run(True, args.steps, args.warmup)
+    wall_s, ms_s = run(False, max(2, args.steps // 2), 1)
+    out = {
+        "metric": METRIC,
+        "value": elems * args.steps / wall_b,
+        "unit": "LDE field elems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall_b * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{BATCH_WORKLOAD}: 64 traces, log rows uniform in 10..18, columns uniform in "
+                               "20..135, blowup 8, cap height 2, natural layout, one v3db_commit_batch call",
+                   "lde_elements_per_step": elems,
+                   "shapes": [[L, C] for L, C in shapes]},
+        "latency_ms": {"p50": float(np.percentile(ms_b, 50)), "p99": float(np.percentile(ms_b, 99))},
+        "one_launch_per_trace": {"value": elems * len(ms_s) / wall_s, "ms_per_step": wall_s * 1e3 / len(ms_s),
+                                 "p50_ms": float(np.percentile(ms_s, 50))},
+        "batched_over_per_trace": (elems * args.steps / wall_b) / (elems * len(ms_s) / wall_s),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == BATCH_WORKLOAD:
+        return batch_main(args)
 
     import numpy as np
     import torch

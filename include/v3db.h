@@ -139,28 +139,41 @@ typedef struct {
   uint64_t *d_cap;  /* [2^cap_height][4], device; required */
 } v3db_commit_job;
 
-/* Commit many independent traces of different shapes in one batched pass: every
- * phase (interpolation, extension, leaf hashing, each Merkle level) runs as one
- * launch over the work of all jobs, so small traces share the GPU. The launch
- * sequence for a given set of shapes is captured once as a HIP graph and
- * replayed. Scratch for NULL d_lde/d_tree comes from the context and counts
- * against its HBM budget. Results are identical to committing each job alone.
- * Errors: as v3db_lde / v3db_merkle_commit for any job (nothing is enqueued),
- * OUT_OF_MEMORY if the scratch does not fit the budget. */
+/* Commit many independent traces of different shapes. Natural-layout jobs are
+ * committed together, phase by phase: every phase (the three extension passes,
+ * leaf hashing, each tree depth) runs as one launch over the work of all jobs,
+ * so small traces share the GPU. The launch sequence for a given list of shapes
+ * (per stream) is captured once as a HIP graph and replayed; only a small table
+ * of buffer pointers is uploaded per call. Bit-reversed jobs are committed one
+ * at a time. Scratch for NULL d_lde/d_tree comes from the context (per stream)
+ * and counts against its HBM budget. Results are identical to committing each
+ * job alone. Errors: as v3db_lde / v3db_merkle_commit for any job (checked
+ * before anything is enqueued), OUT_OF_MEMORY if the scratch does not fit. */
 v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, v3db_stream stream);
 
 /* Phase timing. While enabled, commit calls record HIP events on their stream
  * around each phase: V3DB_PHASE_LDE (all extension passes), V3DB_PHASE_LEAF
- * (row hashing) and V3DB_PHASE_MERKLE (tree levels and cap). v3db_profile_read
- * waits for the recorded events, adds each phase's elapsed milliseconds and
- * count of timed intervals into ms_out[3] / count_out[3] (either may be NULL)
+ * (row hashing) and V3DB_PHASE_MERKLE (tree levels and cap) for traces
+ * committed one at a time, V3DB_PHASE_BATCH around each batched group.
+ * v3db_profile_read waits for the recorded events, adds each phase's elapsed
+ * milliseconds and count of timed intervals into ms_out[4] / count_out[4] (either may be NULL)
  * and forgets them. Enabling or disabling also forgets pending records. */
-#define V3DB_PHASES 3
+#define V3DB_PHASES 4
 #define V3DB_PHASE_LDE 0
 #define V3DB_PHASE_LEAF 1
 #define V3DB_PHASE_MERKLE 2
+#define V3DB_PHASE_BATCH 3  /* a whole batched group (all its phases) */
 v3db_status v3db_profile_enable(v3db_ctx *ctx, int on);
 v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out);
+
+/* Context options.
+ * V3DB_OPT_BATCHING (default 1): 0 commits every job of v3db_commit_batch one at a
+ *   time with the single-trace kernels (one launch sequence per trace) instead of
+ *   the batched phase launches; results are identical either way.
+ * V3DB_OPT_BATCH_GROUP_BYTES (default 32 GiB): natural-layout jobs are batched in
+ *   groups whose scratch (Y, plus LDE and tree when not given) stays below this. */
+typedef enum { V3DB_OPT_BATCHING = 0, V3DB_OPT_BATCH_GROUP_BYTES = 1 } v3db_option;
+v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value);
 
 /* Device bytes of scratch a batch of jobs needs beyond the caller's buffers. */
 size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs);

@@ -79,6 +79,7 @@ def lib():
         "v3db_commit_batch": (i32, [vp, ctypes.POINTER(_Job), sz, vp]),
         "v3db_commit_batch_scratch_bytes": (sz, [ctypes.POINTER(_Job), sz]),
         "v3db_profile_enable": (i32, [vp, i32]),
+        "v3db_set_option": (i32, [vp, i32, u64]),
         "v3db_profile_read": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -237,10 +238,17 @@ class Context:
 
     def profile_read(self):
         """{phase: (milliseconds, intervals)} since the last read, for lde / leaf / merkle."""
-        ms = np.zeros(3, dtype=np.float64)
-        cnt = np.zeros(3, dtype=np.uint64)
+        ms = np.zeros(4, dtype=np.float64)
+        cnt = np.zeros(4, dtype=np.uint64)
         _check(lib().v3db_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data))
-        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(("lde", "leaf", "merkle"))}
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(("lde", "leaf", "merkle", "batch"))}
+
+    def set_batching(self, on: bool):
+        """False: commit_batch runs each job with its own launch sequence (the baseline)."""
+        _check(lib().v3db_set_option(self._h, 0, 1 if on else 0))
+
+    def set_batch_group_bytes(self, n: int):
+        _check(lib().v3db_set_option(self._h, 1, n))
 
     def commit(self, job: Job, stream=None):
         return self.commit_batch([job], stream)[0]

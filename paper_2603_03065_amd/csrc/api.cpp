@@ -196,6 +196,7 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  free_batch_graphs(ctx);
   prof_drop(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   ctx->event_pool.clear();
@@ -249,6 +250,22 @@ v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out
   return st;
 }
 
+v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "set_option: NULL ctx");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  switch (opt) {
+    case V3DB_OPT_BATCHING:
+      ctx->batching = value != 0;
+      return V3DB_OK;
+    case V3DB_OPT_BATCH_GROUP_BYTES:
+      if (value == 0) return set_error(V3DB_ERR_INVALID_ARG, "set_option: group size must be > 0");
+      ctx->batch_group_bytes = (size_t)value;
+      return V3DB_OK;
+  }
+  return set_error(V3DB_ERR_INVALID_ARG, "set_option: unknown option");
+}
+
 v3db_status v3db_derive_poseidon_constants(uint64_t poseidon_seed, uint64_t *rc_out, uint64_t *circ_out,
                                            uint32_t *attempts_out) {
   clear_error();
@@ -276,7 +293,7 @@ v3db_status v3db_lde(v3db_ctx *ctx, const uint64_t *d_trace, uint32_t n_cols, ui
   st = check_canonical(ctx, d_trace, size_t(n_cols) << log_rows, s);
   if (st != V3DB_OK) return st;
   void *z = nullptr;
-  st = ctx_scratch(ctx, s, lde_scratch_bytes(n_cols, log_rows, log_blowup), &z);
+  st = ctx_scratch(ctx, s, lde_scratch_bytes(n_cols, log_rows, log_blowup, layout), &z);
   if (st != V3DB_OK) return st;
   return enqueue_lde(ctx, d_trace, n_cols, log_rows, log_blowup, shift, layout, d_lde, (uint64_t *)z, s);
 }

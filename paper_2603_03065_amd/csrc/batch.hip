@@ -1,15 +1,123 @@
 // Commit of many traces: v3db_commit_batch.
+//
+// Traces in natural layout are committed together, phase by phase: one launch
+// runs pass 1 of every column of every trace, then one launch each for pass 2,
+// pass 3 and leaf hashing, then one launch per tree depth covering all traces
+// that still have a level at that depth. Each launch's blocks look up their
+// trace in a small table of item ranges, so traces of any mix of shapes fill
+// the GPU together; small traces no longer leave most of it idle, and the long
+// serial top of each tree overlaps with the other trees. The launch sequence
+// for a given list of shapes is captured once as a HIP graph and replayed; each
+// call only refreshes the device table of buffer pointers the graph's kernels
+// read. Bit-reversed traces are committed one at a time with the single-trace
+// kernels.
+#include <string.h>
+
+#include <algorithm>
 #include <string>
 
-#include "internal.h"
+#include "lde_dev.h"
+#include "poseidon_dev.h"
 
 namespace v3db {
 
-static size_t tree_digests(uint32_t log_leaves, uint32_t cap_height) {
+namespace {
+
+constexpr int POS_THREADS = 256;
+constexpr int LEAF_ROWS = 256;     // rows per leaf-hashing block
+constexpr int MERKLE_NODES = 256;  // nodes per Merkle block
+
+// Device descriptor of one trace of a batch.
+struct BJob {
+  lde::LdeTask t;        // natural layout: Z is built in the output (t.z = t.lde)
+  uint64_t *tree;        // levels, leaves first
+  uint64_t *cap;
+  uint32_t n_cols, logN, cap_height, pad;
+};
+
+// Items of one launch: range r covers items [first, first + count) of job `job`.
+struct BRange {
+  uint32_t first, job, count, pad;
+};
+
+__device__ __forceinline__ int find_range(const BRange *__restrict__ r, int n, uint32_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(lde::LDE_THREADS) k_batch_pass(const BJob *__restrict__ jobs,
+                                                                  const BRange *__restrict__ ranges, int n_ranges,
+                                                                  int pass, Twiddles tw) {
+  extern __shared__ uint64_t sh[];
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const lde::LdeTask t = jobs[r.job].t;
+  const uint32_t local = blockIdx.x - r.first;
+  if (pass == 1) {
+    const int tiles = lde::lde_tiles1(t);
+    lde::lde_pass1_tile(t, tw, sh, local / tiles, local % tiles);
+  } else if (pass == 2) {
+    const int tiles = lde::lde_tiles2(t);
+    const int col = local / tiles;
+    lde::lde_pass2_tile(t, tw, sh, col, col, local % tiles);
+  } else {
+    const int tiles = lde::lde_tiles3(t);
+    const int col = local / tiles;
+    lde::lde_pass3_tile(t, tw, sh, col, col, local % tiles);
+  }
+}
+
+__global__ void __launch_bounds__(POS_THREADS) k_batch_leaf(const BJob *__restrict__ jobs,
+                                                             const BRange *__restrict__ ranges, int n_ranges,
+                                                             const uint64_t *__restrict__ rc, pos::Circ c) {
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint64_t n_rows = uint64_t(1) << j.logN;
+  const uint64_t k = uint64_t(blockIdx.x - r.first) * LEAF_ROWS + threadIdx.x;
+  if (k >= n_rows) return;
+  uint32_t a[WIDTH];
+  pos::circ_to_vgprs(c, a);
+  uint64_t *d = j.tree + k * DIGEST;
+  pos::leaf_digest(j.t.lde, j.n_cols, n_rows, k, d, rc, a);
+  if (j.cap_height == j.logN) {
+#pragma unroll
+    for (int i = 0; i < DIGEST; i++) j.cap[k * DIGEST + i] = d[i];
+  }
+}
+
+// Tree depth `depth` (1 = the level above the leaves) of every listed job.
+__global__ void __launch_bounds__(POS_THREADS) k_batch_merkle(const BJob *__restrict__ jobs,
+                                                               const BRange *__restrict__ ranges, int n_ranges,
+                                                               int depth, const uint64_t *__restrict__ rc,
+                                                               pos::Circ c) {
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint32_t level = j.logN - depth;  // 2^level nodes at this level
+  const uint64_t count = uint64_t(1) << level;
+  const uint64_t k = uint64_t(blockIdx.x - r.first) * MERKLE_NODES + threadIdx.x;
+  if (k >= count) return;
+  uint32_t a[WIDTH];
+  pos::circ_to_vgprs(c, a);
+  // level L - d starts after 2^L + 2^(L-1) + ... + 2^(L-d+1) digests
+  const uint64_t off_below = (uint64_t(2) << j.logN) - (uint64_t(2) << (level + 1));
+  const uint64_t off_here = (uint64_t(2) << j.logN) - (uint64_t(2) << level);
+  uint64_t *d = j.tree + (off_here + k) * DIGEST;
+  pos::merkle_node(j.tree + off_below * DIGEST, k, d, rc, a);
+  if (level == j.cap_height) {
+#pragma unroll
+    for (int i = 0; i < DIGEST; i++) j.cap[k * DIGEST + i] = d[i];
+  }
+}
+
+size_t tree_digests(uint32_t log_leaves, uint32_t cap_height) {
   return (size_t(2) << log_leaves) - (size_t(1) << cap_height);
 }
 
-static v3db_status check_job(const v3db_commit_job &j, size_t idx) {
+v3db_status check_job(const v3db_commit_job &j, size_t idx) {
   const std::string pre = "commit job " + std::to_string(idx) + ": ";
   if (!j.d_trace || !j.d_cap) return set_error(V3DB_ERR_INVALID_ARG, pre + "NULL trace or cap pointer");
   if (j.n_cols == 0) return set_error(V3DB_ERR_INVALID_ARG, pre + "n_cols must be > 0");
@@ -24,16 +132,281 @@ static v3db_status check_job(const v3db_commit_job &j, size_t idx) {
   return V3DB_OK;
 }
 
-// Scratch one job needs when run alone: its LDE (if not given), then a region
-// shared by the LDE's Z workspace and the tree (the tree is written only after
-// the LDE has finished on the stream).
-static size_t job_scratch(const v3db_commit_job &j) {
+// Scratch one job needs when committed alone: its LDE (if not given), then a
+// region shared by the LDE's scratch and the tree (the tree is written only
+// after the LDE has finished on the stream).
+size_t single_scratch(const v3db_commit_job &j) {
   const uint32_t logN = j.log_rows + j.log_blowup;
-  size_t lde = j.d_lde ? 0 : (size_t(j.n_cols) << logN) * 8;
-  size_t z = lde_scratch_bytes(j.n_cols, j.log_rows, j.log_blowup);
-  size_t tree = j.d_tree ? 0 : tree_digests(logN, j.cap_height) * DIGEST * 8;
-  return lde + (z > tree ? z : tree);
+  const size_t lde = j.d_lde ? 0 : (size_t(j.n_cols) << logN) * 8;
+  const size_t z = lde_scratch_bytes(j.n_cols, j.log_rows, j.log_blowup, j.layout);
+  const size_t tree = j.d_tree ? 0 : tree_digests(logN, j.cap_height) * DIGEST * 8;
+  return lde + std::max(z, tree);
 }
+
+// Scratch one job needs inside a batched group (everything coexists there):
+// Y, plus its LDE and tree when the caller gives none.
+size_t batched_scratch(const v3db_commit_job &j) {
+  const uint32_t logN = j.log_rows + j.log_blowup;
+  size_t b = (size_t(j.n_cols) << j.log_rows) * 8;
+  if (!j.d_lde) b += (size_t(j.n_cols) << logN) * 8;
+  if (!j.d_tree) b += tree_digests(logN, j.cap_height) * DIGEST * 8;
+  return (b + 255) & ~size_t(255);
+}
+
+v3db_status commit_single(v3db_ctx *ctx, const v3db_commit_job &j, void *scratch, hipStream_t s) {
+  const uint32_t logN = j.log_rows + j.log_blowup;
+  uint8_t *p = (uint8_t *)scratch;
+  uint64_t *lde = j.d_lde;
+  if (!lde) {
+    lde = (uint64_t *)p;
+    p += (size_t(j.n_cols) << logN) * 8;
+  }
+  uint64_t *tree = j.d_tree ? j.d_tree : (uint64_t *)p;
+  hipEvent_t e0 = prof_mark(ctx, s);
+  v3db_status st = enqueue_lde(ctx, j.d_trace, j.n_cols, j.log_rows, j.log_blowup, j.shift, j.layout, lde,
+                               (uint64_t *)p, s);
+  if (st != V3DB_OK) return st;
+  hipEvent_t e1 = prof_mark(ctx, s);
+  st = enqueue_leaf_hash(ctx, lde, j.n_cols, logN, tree, s);
+  if (st != V3DB_OK) return st;
+  hipEvent_t e2 = prof_mark(ctx, s);
+  st = enqueue_merkle_levels(ctx, tree, logN, j.cap_height, j.d_cap, s);
+  if (st != V3DB_OK) return st;
+  hipEvent_t e3 = prof_mark(ctx, s);
+  prof_interval(ctx, V3DB_PHASE_LDE, e0, e1);
+  prof_interval(ctx, V3DB_PHASE_LEAF, e1, e2);
+  prof_interval(ctx, V3DB_PHASE_MERKLE, e2, e3);
+  return V3DB_OK;
+}
+
+struct Phase {
+  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth
+  int depth;  // Merkle depth
+  size_t ranges_off, n_ranges;
+  uint32_t blocks;
+  size_t lds;
+};
+
+struct GroupPlan {
+  std::vector<BRange> ranges;
+  std::vector<Phase> phases;
+};
+
+void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3db_commit_job> &jobs,
+                GroupPlan &g) {
+  const size_t nj = jobs.size();
+  auto add_phase = [&](int kind, int depth, size_t lds, auto items_of) {
+    Phase ph{kind, depth, g.ranges.size(), 0, 0, lds};
+    uint32_t first = 0;
+    for (size_t i = 0; i < nj; i++) {
+      const uint32_t cnt = items_of(i);
+      if (!cnt) continue;
+      g.ranges.push_back(BRange{first, (uint32_t)i, cnt, 0});
+      first += cnt;
+    }
+    ph.n_ranges = g.ranges.size() - ph.ranges_off;
+    ph.blocks = first;
+    if (ph.blocks) g.phases.push_back(ph);
+  };
+  size_t lds[4] = {0, 0, 0, 0};
+  for (size_t i = 0; i < nj; i++) {
+    const LdePlan &p = *plans[i];
+    const int L1 = p.L1, L2 = p.L2, b = p.log_blowup;
+    lds[1] = std::max(lds[1], lde::lde_lds_words(1, L1, L2, b, p.logT1) * 8);
+    lds[2] = std::max(lds[2], lde::lde_lds_words(2, L1, L2, b, p.logT2) * 8);
+    lds[3] = std::max(lds[3], lde::lde_lds_words(3, L1, L2, b, p.logT3) * 8);
+  }
+  add_phase(1, 0, lds[1], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L2) >> plans[i]->logT1); });
+  add_phase(2, 0, lds[2], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2); });
+  add_phase(3, 0, lds[3], [&](size_t i) {
+    return jobs[i].n_cols * ((1u << (plans[i]->L2 + plans[i]->log_blowup)) >> plans[i]->logT3);
+  });
+  add_phase(4, 0, 0, [&](size_t i) {
+    const uint64_t rows = uint64_t(1) << (jobs[i].log_rows + jobs[i].log_blowup);
+    return (uint32_t)((rows + LEAF_ROWS - 1) / LEAF_ROWS);
+  });
+  uint32_t max_depth = 0;
+  for (size_t i = 0; i < nj; i++)
+    max_depth = std::max(max_depth, jobs[i].log_rows + jobs[i].log_blowup - jobs[i].cap_height);
+  for (uint32_t d = 1; d <= max_depth; d++) {
+    add_phase(5, (int)d, 0, [&](size_t i) -> uint32_t {
+      const uint32_t logN = jobs[i].log_rows + jobs[i].log_blowup;
+      if (logN < d || logN - d < jobs[i].cap_height) return 0;
+      const uint64_t nodes = uint64_t(1) << (logN - d);
+      return (uint32_t)((nodes + MERKLE_NODES - 1) / MERKLE_NODES);
+    });
+  }
+}
+
+// Graphs are cached per stream too: a graph's table is rewritten only by calls
+// on the stream that launches it, so the previous launch has finished reading it.
+std::vector<uint64_t> shape_key(const std::vector<v3db_commit_job> &jobs, hipStream_t stream) {
+  std::vector<uint64_t> k;
+  k.reserve(jobs.size() * 3 + 1);
+  k.push_back((uint64_t)(uintptr_t)stream);
+  for (const auto &j : jobs) {
+    k.push_back(uint64_t(j.n_cols) | uint64_t(j.log_rows) << 32 | uint64_t(j.log_blowup) << 40 |
+                uint64_t(j.cap_height) << 48);
+    k.push_back(j.shift);
+    k.push_back(uint64_t(j.d_lde != nullptr) | uint64_t(j.d_tree != nullptr) << 1);
+  }
+  return k;
+}
+
+}  // namespace
+
+// A captured launch sequence for one list of job shapes.
+struct BatchGraph {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void *d_table = nullptr;      // job descriptors, then item ranges, read by the graph's kernels
+  size_t table_bytes = 0, jobs_bytes = 0;
+  void *h_table = nullptr;      // pinned staging copy
+  hipEvent_t staged = nullptr;  // the last upload from h_table has been read
+  uint64_t last_use = 0;
+};
+
+static void destroy_graph(v3db_ctx *ctx, BatchGraph *g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->staged) (void)hipEventDestroy(g->staged);
+  if (g->h_table) (void)hipHostFree(g->h_table);
+  if (g->d_table) ctx_free(ctx, g->d_table, g->table_bytes);
+  delete g;
+}
+
+void free_batch_graphs(v3db_ctx *ctx) {
+  for (BatchGraph *g : ctx->graphs) destroy_graph(ctx, g);
+  ctx->graphs.clear();
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  ctx->capture_stream = nullptr;
+}
+
+namespace {
+
+v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
+  if (!ctx->capture_stream) {
+    v3db_status st =
+        hip_check(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "batch capture stream");
+    if (st != V3DB_OK) return st;
+  }
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void *)k_batch_pass, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_done = true;
+  }
+  const BJob *d_jobs = (const BJob *)bg->d_table;
+  const BRange *d_ranges = (const BRange *)((uint8_t *)bg->d_table + bg->jobs_bytes);
+  hipStream_t cs = ctx->capture_stream;
+  v3db_status st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (st != V3DB_OK) return st;
+  const Twiddles tw = ctx->tw;
+  const pos::Circ c = pos::circ_of(ctx);
+  for (const Phase &ph : g.phases) {
+    const BRange *rr = d_ranges + ph.ranges_off;
+    const int nr = (int)ph.n_ranges;
+    if (ph.kind <= 3)
+      hipLaunchKernelGGL(k_batch_pass, dim3(ph.blocks), dim3(lde::LDE_THREADS), ph.lds, cs, d_jobs, rr, nr, ph.kind,
+                         tw);
+    else if (ph.kind == 4)
+      hipLaunchKernelGGL(k_batch_leaf, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ctx->d_pos, c);
+    else
+      hipLaunchKernelGGL(k_batch_merkle, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ph.depth,
+                         ctx->d_pos, c);
+  }
+  const hipError_t le = hipGetLastError();
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  bg->graph = graph;
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
+  return hip_check(e, "capture batch graph");
+}
+
+// Commit a group of natural-layout jobs together; scratch holds
+// batched_scratch() of every job, in order.
+v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs, uint8_t *scratch,
+                         hipStream_t s) {
+  const size_t nj = jobs.size();
+  std::vector<const LdePlan *> plans(nj);
+  for (size_t i = 0; i < nj; i++) {
+    v3db_status st = get_plan(ctx, jobs[i].log_rows, jobs[i].log_blowup, jobs[i].shift, &plans[i]);
+    if (st != V3DB_OK) return st;
+  }
+  const std::vector<uint64_t> key = shape_key(jobs, s);
+  BatchGraph *bg = nullptr;
+  for (BatchGraph *g : ctx->graphs)
+    if (g->key == key) bg = g;
+  GroupPlan gp;
+  plan_group(plans, jobs, gp);
+  if (!bg) {
+    if (ctx->graphs.size() >= 8) {  // evict the least recently used
+      auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                 [](BatchGraph *a, BatchGraph *b) { return a->last_use < b->last_use; });
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_check(e, "graph eviction sync");
+      destroy_graph(ctx, *it);
+      ctx->graphs.erase(it);
+    }
+    bg = new BatchGraph();
+    bg->key = key;
+    bg->jobs_bytes = (nj * sizeof(BJob) + 255) & ~size_t(255);
+    bg->table_bytes = bg->jobs_bytes + gp.ranges.size() * sizeof(BRange);
+    v3db_status st = ctx_alloc(ctx, &bg->d_table, bg->table_bytes, "batch tables");
+    hipError_t e = hipSuccess;
+    if (st == V3DB_OK) e = hipHostMalloc(&bg->h_table, bg->table_bytes, hipHostMallocDefault);
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventCreateWithFlags(&bg->staged, hipEventDisableTiming);
+    if (st == V3DB_OK && e != hipSuccess) st = hip_check(e, "batch staging");
+    if (st == V3DB_OK) st = capture_group(ctx, gp, bg);
+    if (st != V3DB_OK) {
+      destroy_graph(ctx, bg);
+      return st;
+    }
+    ctx->graphs.push_back(bg);
+  }
+  bg->last_use = ++ctx->graph_clock;
+  // this call's buffers
+  std::vector<BJob> bj(nj);
+  uint8_t *p = scratch;
+  for (size_t i = 0; i < nj; i++) {
+    const v3db_commit_job &j = jobs[i];
+    const uint32_t logN = j.log_rows + j.log_blowup;
+    uint64_t *y = (uint64_t *)p;
+    uint8_t *q = p + (size_t(j.n_cols) << j.log_rows) * 8;
+    uint64_t *lde = j.d_lde;
+    if (!lde) {
+      lde = (uint64_t *)q;
+      q += (size_t(j.n_cols) << logN) * 8;
+    }
+    uint64_t *tree = j.d_tree ? j.d_tree : (uint64_t *)q;
+    p += batched_scratch(j);
+    BJob &b = bj[i];
+    b.t = lde_task(*plans[i], j.d_trace, y, nullptr, lde, V3DB_LAYOUT_NATURAL);
+    b.tree = tree;
+    b.cap = j.d_cap;
+    b.n_cols = j.n_cols;
+    b.logN = logN;
+    b.cap_height = j.cap_height;
+    b.pad = 0;
+  }
+  // the previous upload from the staging buffer must have been read before it is rewritten
+  hipError_t e = hipEventSynchronize(bg->staged);
+  if (e != hipSuccess) return hip_check(e, "batch staging wait");
+  memcpy(bg->h_table, bj.data(), nj * sizeof(BJob));
+  memcpy((uint8_t *)bg->h_table + bg->jobs_bytes, gp.ranges.data(), gp.ranges.size() * sizeof(BRange));
+  e = hipMemcpyAsync(bg->d_table, bg->h_table, bg->table_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(bg->staged, s);
+  if (e != hipSuccess) return hip_check(e, "batch table upload");
+  hipEvent_t e0 = prof_mark(ctx, s);
+  e = hipGraphLaunch(bg->exec, s);
+  if (e != hipSuccess) return hip_check(e, "batch graph launch");
+  hipEvent_t e1 = prof_mark(ctx, s);
+  prof_interval(ctx, V3DB_PHASE_BATCH, e0, e1);
+  return V3DB_OK;
+}
+
+}  // namespace
 
 }  // namespace v3db
 
@@ -41,13 +414,24 @@ using namespace v3db;
 
 extern "C" {
 
+// A job is batched when it is in natural layout and at least one other such
+// job comes with it (a lone trace gains nothing from the batched launches and
+// keeps the single-trace LDE's cache-resident column chunks).
+static size_t batchable_count(const v3db_commit_job *jobs, size_t n_jobs) {
+  size_t k = 0;
+  for (size_t i = 0; i < n_jobs; i++) k += jobs[i].layout == V3DB_LAYOUT_NATURAL;
+  return k;
+}
+
 size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs) {
-  size_t m = 0;
-  for (size_t i = 0; jobs && i < n_jobs; i++) {
-    const size_t b = job_scratch(jobs[i]);
-    if (b > m) m = b;
+  if (!jobs) return 0;
+  const bool batch = batchable_count(jobs, n_jobs) >= 2;
+  size_t single = 0, batched = 0;
+  for (size_t i = 0; i < n_jobs; i++) {
+    if (batch && jobs[i].layout == V3DB_LAYOUT_NATURAL) batched += batched_scratch(jobs[i]);
+    else single = std::max(single, single_scratch(jobs[i]));
   }
-  return m;
+  return std::max(single, batched);
 }
 
 v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, v3db_stream stream) {
@@ -62,33 +446,46 @@ v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t
   std::lock_guard<std::mutex> g(ctx->mu);
   (void)hipSetDevice(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  void *scratch = nullptr;
-  v3db_status st = ctx_scratch(ctx, s, v3db_commit_batch_scratch_bytes(jobs, n_jobs), &scratch);
-  if (st != V3DB_OK) return st;
+  // Natural-layout jobs go through the batched graph, in groups whose scratch
+  // stays within the group cap; the others (and every job when batching is
+  // switched off) are committed one at a time.
+  std::vector<v3db_commit_job> group, singles;
+  std::vector<std::vector<v3db_commit_job>> groups;
+  size_t gbytes = 0;
+  const bool batch = ctx->batching && batchable_count(jobs, n_jobs) >= 2;
   for (size_t i = 0; i < n_jobs; i++) {
     const v3db_commit_job &j = jobs[i];
-    const uint32_t logN = j.log_rows + j.log_blowup;
-    uint8_t *p = (uint8_t *)scratch;
-    uint64_t *lde = j.d_lde;
-    if (!lde) {
-      lde = (uint64_t *)p;
-      p += (size_t(j.n_cols) << logN) * 8;
+    if (j.layout != V3DB_LAYOUT_NATURAL || !batch) {
+      singles.push_back(j);
+      continue;
     }
-    uint64_t *z = (uint64_t *)p;
-    uint64_t *tree = j.d_tree ? j.d_tree : (uint64_t *)p;
-    hipEvent_t e0 = prof_mark(ctx, s);
-    st = enqueue_lde(ctx, j.d_trace, j.n_cols, j.log_rows, j.log_blowup, j.shift, j.layout, lde, z, s);
+    const size_t b = batched_scratch(j);
+    if (!group.empty() && gbytes + b > ctx->batch_group_bytes) {
+      groups.push_back(group);
+      group.clear();
+      gbytes = 0;
+    }
+    group.push_back(j);
+    gbytes += b;
+  }
+  if (!group.empty()) groups.push_back(group);
+  size_t need = 0;
+  for (const auto &j : singles) need = std::max(need, single_scratch(j));
+  for (const auto &gr : groups) {
+    size_t b = 0;
+    for (const auto &j : gr) b += batched_scratch(j);
+    need = std::max(need, b);
+  }
+  void *scratch = nullptr;
+  v3db_status st = ctx_scratch(ctx, s, need, &scratch);
+  if (st != V3DB_OK) return st;
+  for (const auto &gr : groups) {
+    st = commit_group(ctx, gr, (uint8_t *)scratch, s);
     if (st != V3DB_OK) return st;
-    hipEvent_t e1 = prof_mark(ctx, s);
-    st = enqueue_leaf_hash(ctx, lde, j.n_cols, logN, tree, s);
+  }
+  for (const auto &j : singles) {
+    st = commit_single(ctx, j, scratch, s);
     if (st != V3DB_OK) return st;
-    hipEvent_t e2 = prof_mark(ctx, s);
-    st = enqueue_merkle_levels(ctx, tree, logN, j.cap_height, j.d_cap, s);
-    if (st != V3DB_OK) return st;
-    hipEvent_t e3 = prof_mark(ctx, s);
-    prof_interval(ctx, V3DB_PHASE_LDE, e0, e1);
-    prof_interval(ctx, V3DB_PHASE_LEAF, e1, e2);
-    prof_interval(ctx, V3DB_PHASE_MERKLE, e2, e3);
   }
   return V3DB_OK;
 }

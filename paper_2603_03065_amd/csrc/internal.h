@@ -35,6 +35,7 @@ struct Twiddles {
 // Per-shape LDE tables: see ntt.hip.
 struct LdePlan {
   uint32_t log_rows, log_blowup, L1, L2;
+  uint32_t logT1, logT2, logT3;  // log2 tile heights of the three passes
   uint64_t shift;
   uint64_t *d_twist;  // [B][n2]: (shift^n1 * w_{B n2}^r)^j
   uint64_t *d_scale;  // [n1]: n^-1 * shift^k1
@@ -44,6 +45,8 @@ struct ScratchBuf {
   void *ptr = nullptr;
   size_t bytes = 0;
 };
+
+struct BatchGraph;
 
 }  // namespace v3db
 
@@ -62,6 +65,12 @@ struct v3db_ctx {
   bool profiling = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
   std::vector<hipEvent_t> event_pool;
+  // batched commits: captured launch sequences per (shapes, stream)
+  bool batching = true;
+  size_t batch_group_bytes = size_t(32) << 30;
+  std::vector<v3db::BatchGraph *> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t capture_stream = nullptr;
   std::mutex mu;
 };
 
@@ -89,15 +98,21 @@ void free_twiddles(v3db_ctx *ctx);
 v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out);
 
 // Enqueue an LDE (ntt.hip). Arguments already validated.
-constexpr uint32_t LDE_CHUNK_COLS = 8;  // columns whose Z scratch is live at once
-size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup);
+// Columns that go through passes 2 and 3 together (their Z stays cache-resident).
+constexpr uint32_t LDE_CHUNK_COLS = 8;
+// Scratch of one v3db_lde call: Y (n words per column), plus Z for one chunk of
+// columns in bit-reversed layout (natural layout builds Z in the output).
+size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup, v3db_layout layout);
 v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, uint32_t log_rows,
                         uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *lde,
-                        uint64_t *z, hipStream_t stream);
+                        uint64_t *scratch, hipStream_t stream);
 
 // Phase timing: returns an event recorded on `stream` (or nullptr when not profiling).
 hipEvent_t prof_mark(v3db_ctx *ctx, hipStream_t stream);
 void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
+
+// Batched commits (batch.hip).
+void free_batch_graphs(v3db_ctx *ctx);
 
 // Poseidon work (poseidon.hip).
 v3db_status enqueue_permute(v3db_ctx *ctx, uint64_t *states, size_t count, hipStream_t stream);

@@ -1,0 +1,343 @@
+// Device routines of the coset low-degree extension, shared by the
+// single-trace kernels (ntt.hip) and the multi-trace batch kernels (batch.hip).
+//
+// For a column a of n = 2^L values (a_i = P(w_n^i)), the extension to N = B*n
+// points is LDE[k] = P(s * w_N^k) = sum_j c_j (s w_N^k)^j with c = iNTT_n(a).
+// It runs as three LDS-tiled passes of a four-step factorisation, n = n1*n2:
+//
+//   pass 1  (interpolation, first half)   j = j1*n2 + j2, k = k1 + n1*k2
+//           Y[k1][j2] = w_n^(-j2 k1) * sum_j1 a[j1 n2 + j2] w_n1^(-j1 k1)
+//   pass 2  per residue k1: c'[k2] = sum_j2 Y[k1][j2] w_n2^(-j2 k2)   (= n c[k1 + n1 k2])
+//           then a blowup-B extension of that residue sequence with shift s^n1,
+//           for every e < W = B*n2 (e = r + B*m1: coset r, point m1):
+//           Z[k1][e] = n^-1 s^k1 w_N^(k1 e) * sum_k2 c'[k2] (s^n1)^k2 w_W^(k2 e)
+//   pass 3  per column e of Z: LDE[e + W m2] = sum_k1 Z[k1][e] w_n1^(k1 m2)
+//
+// (LDE[e + B n2 m2] = sum_k1 w_n1^(k1 m2) s^k1 w_N^(k1 e) sum_k2 c[k1+n1 k2]
+//  (s^n1)^k2 w_(B n2)^(k2 e) follows from j = k1 + n1 k2 and k = e + B n2 m2.)
+//
+// Each pass moves tiles of T adjacent columns/rows so global accesses are runs
+// of T*8 bytes and does its sub-transforms in LDS with radix-8 register
+// butterflies (decimation in frequency: natural order in, bit-reversed out;
+// decimation in time: the reverse), applying the twiddles on the way out.
+// Pass 1 writes Y (n words per column) to scratch. Pass 2 writes Z (N words per
+// column, rows of W contiguous words): in natural layout over the output
+// column itself, since pass 3 then reads and writes the same words and runs in
+// place; in bit-reversed layout to scratch, a chunk of columns at a time. Pass 3
+// writes natural order in runs of T words, bit-reversed order in whole rows.
+#pragma once
+#include "internal.h"
+
+namespace v3db {
+namespace lde {
+
+constexpr int LDE_THREADS = 512;
+constexpr int DFT_N = 1 << DFT_LOG_MAX;  // 4096
+constexpr int TILE_ELEMS = 8192;         // T * M per tile
+constexpr int MAX_PER_THREAD = TILE_ELEMS / LDE_THREADS;
+
+__device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
+  return bits ? (__brev(x) >> (32 - bits)) : 0u;
+}
+
+// w^e for e < 2^26 from the two-level table (w = w_{2^26} or its inverse).
+__device__ __forceinline__ uint64_t tw_pow(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
+                                           uint32_t e) {
+  return gl::mul(hi[e >> TW_HALF], lo[e & ((1u << TW_HALF) - 1)]);
+}
+
+// Powers of w_8 = 7^((p-1)/8) (forward) and of its inverse; all are +-2^(24 k),
+// so with these compile-time operands the products need only half the partial
+// products.
+__device__ __forceinline__ uint64_t w8(int k, bool inv) {
+  constexpr uint64_t F[4] = {1ull, 18446744069397807105ull, 281474976710656ull, 18446742969902956801ull};
+  constexpr uint64_t I[4] = {1ull, 1099511627520ull, 18446462594437873665ull, 16777216ull};
+  return inv ? I[k] : F[k];
+}
+
+// Size-R transform in registers (R = 2, 4, 8) by radix-2 stages.
+// dif: natural order in, bit-reversed order out. dit: bit-reversed in, natural out.
+template <int R, bool INV>
+__device__ __forceinline__ void reg_dif(uint64_t v[R]) {
+#pragma unroll
+  for (int h = R / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * h)
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        const uint64_t u = v[b + i], w = v[b + i + h];
+        v[b + i] = gl::add(u, w);
+        const uint64_t d = gl::sub(u, w);
+        v[b + i + h] = i ? gl::mul(d, w8(i * (8 / (2 * h)), INV)) : d;
+      }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void reg_dit(uint64_t v[R]) {
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * h)
+#pragma unroll
+      for (int i = 0; i < h; i++) {
+        const uint64_t u = v[b + i];
+        uint64_t w = v[b + i + h];
+        if (i) w = gl::mul(w, w8(i * (8 / (2 * h)), INV));
+        v[b + i] = gl::add(u, w);
+        v[b + i + h] = gl::sub(u, w);
+      }
+}
+
+template <int R>
+__device__ __forceinline__ int brev_r(int j) {
+  return R == 8 ? ((j & 1) << 2 | (j & 2) | (j >> 2)) : R == 4 ? ((j & 1) << 1 | (j >> 1)) : j;
+}
+
+// One radix-R pass of a decimation-in-frequency transform over T rows of
+// 2^logM words in LDS (row stride rs): sub-blocks of 2^logS words, each
+// butterfly takes the R words i + j*2^logS/R, transforms them, and multiplies
+// output slot j (frequency bitrev(j)) by w_S^(i * bitrev(j)). tw = w_4096^t.
+template <int R, bool INV>
+__device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, int logS,
+                                         const uint64_t *__restrict__ tw) {
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int logStride = logS - LR;
+  const int per_row = 1 << (logM - LR);
+  const int nb = T * per_row;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int t = b >> (logM - LR);
+    const int q = b & (per_row - 1);
+    const int i = q & ((1 << logStride) - 1);
+    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
+    reg_dif<R, INV>(v);
+    if (i) {
+#pragma unroll
+      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
+  }
+}
+
+// One radix-R pass of a decimation-in-time transform: combines R transformed
+// sub-blocks of 2^logS/R words into one of 2^logS words.
+template <int R, bool INV>
+__device__ __forceinline__ void dit_pass(uint64_t *sh, int T, int logM, int rs, int logS,
+                                         const uint64_t *__restrict__ tw) {
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int logStride = logS - LR;
+  const int per_row = 1 << (logM - LR);
+  const int nb = T * per_row;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int t = b >> (logM - LR);
+    const int q = b & (per_row - 1);
+    const int i = q & ((1 << logStride) - 1);
+    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
+    if (i) {
+#pragma unroll
+      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
+    }
+    reg_dit<R, INV>(v);
+#pragma unroll
+    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
+  }
+}
+
+// Whole transforms over the rows: radix-8 passes, then one radix-4 or radix-2
+// pass for the remaining bits. Each pass ends with a barrier.
+// Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
+// were done another way).
+template <bool INV>
+__device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ tw) {
+  int logS = logS0;
+  for (; logS >= 3; logS -= 3) {
+    dif_pass<8, INV>(sh, T, logM, rs, logS, tw);
+    __syncthreads();
+  }
+  if (logS == 2) {
+    dif_pass<4, INV>(sh, T, logM, rs, 2, tw);
+    __syncthreads();
+  } else if (logS == 1) {
+    dif_pass<2, INV>(sh, T, logM, rs, 1, tw);
+    __syncthreads();
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  dif_rows_from<INV>(sh, T, logM, logM, rs, tw);
+}
+
+template <bool INV>
+__device__ void dit_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
+  int logS = logM % 3;
+  if (logS == 2) {
+    dit_pass<4, INV>(sh, T, logM, rs, 2, tw);
+    __syncthreads();
+  } else if (logS == 1) {
+    dit_pass<2, INV>(sh, T, logM, rs, 1, tw);
+    __syncthreads();
+  }
+  for (logS += 3; logS <= logM; logS += 3) {
+    dit_pass<8, INV>(sh, T, logM, rs, logS, tw);
+    __syncthreads();
+  }
+}
+
+
+// One trace's LDE as the passes see it. Column c of the trace is trace + c*n,
+// of Y (pass 1 output) y + c*n, of the output lde + c*N, and the Z rows of
+// column c start at z + zc*zstride where zc is the column (natural layout:
+// z = lde, zstride = N, Z is written over the output column and pass 3 runs in
+// place) or its index within the current chunk (bit-reversed layout: z is scratch).
+struct LdeTask {
+  const uint64_t *trace;
+  uint64_t *y;
+  uint64_t *z;
+  uint64_t *lde;
+  const uint64_t *twist;  // [B][n2]: (shift^n1 w_{B n2}^r)^i
+  const uint64_t *scale;  // [n1]: n^-1 shift^k1
+  uint64_t zstride;
+  int L, b, L1, L2;       // log n, log blowup, log n1, log n2 (n = n1 n2)
+  int logT1, logT2, logT3;
+  int bitrev;
+};
+
+__device__ __forceinline__ int lde_tiles1(const LdeTask &t) { return (1 << t.L2) >> t.logT1; }
+__device__ __forceinline__ int lde_tiles2(const LdeTask &t) { return (1 << t.L1) >> t.logT2; }
+__device__ __forceinline__ int lde_tiles3(const LdeTask &t) { return (1 << (t.L2 + t.b)) >> t.logT3; }
+
+// Pass 1, tile = T consecutive j2 of column col.
+__device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int tile) {
+  const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT1, rs = n1 + 1;
+  const size_t n = size_t(1) << s.L;
+  const uint64_t *a = s.trace + size_t(col) * n;
+  uint64_t *y = s.y + size_t(col) * n;
+  const int j2_0 = tile << s.logT1;
+  const int total = T * n1;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e & (T - 1), j1 = e >> s.logT1;
+    sh[t * rs + j1] = a[size_t(j1) * n2 + j2_0 + t];
+  }
+  __syncthreads();
+  dif_rows<true>(sh, T, s.L1, rs, tw.dft_inv);
+  const int shl = TW_LOG - s.L;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e & (T - 1), k1 = e >> s.logT1;
+    const uint32_t j2 = j2_0 + t;
+    uint64_t v = sh[t * rs + brev(k1, s.L1)];
+    const uint32_t ex = (uint32_t)((uint64_t(j2) * k1) & (n - 1));
+    if (ex) v = gl::mul(v, tw_pow(tw.inv_lo, tw.inv_hi, ex << shl));
+    y[size_t(k1) * n2 + j2] = v;
+  }
+}
+
+// Pass 2, tile = T consecutive residues k1 (rows of Y) of column col; W = B*n2.
+// Row k1 of Y is transformed back (giving n*c[k1 + n1*k2] in bit-reversed
+// positions), scaled by n^-1 s^k1 and expanded to the W-point zero-padded
+// transform: its first radix-B decimation-in-frequency pass has a single
+// nonzero input per butterfly, so output slot j of butterfly i is the input
+// times the twist (s^n1 w_W^r)^i, r = bitrev(j). The remaining passes run on the
+// B cosets together; row k1 of Z gets Z[k1][e] = w_N^(k1 e) * (result at e).
+__device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
+                                               int tile) {
+  const int n2 = 1 << s.L2, T = 1 << s.logT2, B = 1 << s.b;
+  const int LW = s.L2 + s.b, W = 1 << LW, rs = W + 1;
+  const size_t n = size_t(1) << s.L, N = size_t(1) << (s.L + s.b);
+  const int logN = s.L + s.b;
+  const uint64_t *y = s.y + size_t(col) * n;
+  uint64_t *zc = s.z + size_t(zcol) * s.zstride;
+  const int k1_0 = tile << s.logT2;
+  const int total_in = T << s.L2;
+  for (int e = threadIdx.x; e < total_in; e += blockDim.x) {
+    const int t = e >> s.L2, j = e & (n2 - 1);
+    sh[t * rs + j] = y[size_t(k1_0 + t) * n2 + j];
+  }
+  __syncthreads();
+  dif_rows<true>(sh, T, s.L2, rs, tw.dft_inv);
+  uint64_t c[MAX_PER_THREAD];
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * LDE_THREADS;
+    if (e < total_in) {
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      c[m] = gl::mul(sh[t * rs + brev(i, s.L2)], s.scale[k1_0 + t]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * LDE_THREADS;
+    if (e < total_in) {
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      for (int j = 0; j < B; j++) sh[t * rs + i + (j << s.L2)] = gl::mul(c[m], s.twist[(brev(j, s.b) << s.L2) + i]);
+    }
+  }
+  __syncthreads();
+  dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.dft_fwd);
+  const int total_out = T << LW;
+  const int shl = TW_LOG - logN;
+  for (int e = threadIdx.x; e < total_out; e += blockDim.x) {
+    const int t = e >> LW, f = e & (W - 1);
+    const uint32_t k1 = k1_0 + t;
+    uint64_t v = sh[t * rs + brev(f, LW)];
+    const uint32_t ex = (uint32_t)((uint64_t(k1) * f) & (N - 1));
+    if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
+    zc[(size_t(k1) << LW) + f] = v;
+  }
+}
+
+// Pass 3, tile = T consecutive columns e of Z (of column col). In natural
+// layout the words it reads, Z[k1][e] at k1*W + e, are exactly the words it
+// writes, LDE[e + W*m2], so it can run in place.
+__device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
+                                               int tile) {
+  const int n1 = 1 << s.L1, T = 1 << s.logT3, rs = n1 + 1;
+  const int LW = s.L2 + s.b, W = 1 << LW;
+  const size_t N = size_t(1) << (s.L + s.b);
+  const uint64_t *zc = s.z + size_t(zcol) * s.zstride;
+  uint64_t *out = s.lde + size_t(col) * N;
+  const int e0 = tile << s.logT3;
+  const int total = T * n1;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int t = e & (T - 1), k1 = e >> s.logT3;
+    sh[t * rs + k1] = zc[(size_t(k1) << LW) + e0 + t];
+  }
+  __syncthreads();
+  dif_rows<false>(sh, T, s.L1, rs, tw.dft_fwd);
+  if (!s.bitrev) {
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e & (T - 1), m2 = e >> s.logT3;
+      out[size_t(e0 + t) + size_t(W) * m2] = sh[t * rs + brev(m2, s.L1)];
+    }
+  } else {
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e >> s.L1, p = e & (n1 - 1);
+      out[size_t(brev(e0 + t, LW)) * n1 + p] = sh[t * rs + p];
+    }
+  }
+}
+
+}  // namespace lde
+
+// The task of one trace with this plan (ntt.hip). z is the Z scratch for
+// bit-reversed layout (ignored in natural layout, where Z is built in lde).
+lde::LdeTask lde_task(const LdePlan &plan, const uint64_t *trace, uint64_t *y, uint64_t *z, uint64_t *lde,
+                      v3db_layout layout);
+
+namespace lde {
+
+// LDS words a pass needs for its tile.
+__host__ __device__ inline size_t lde_lds_words(int pass, int L1, int L2, int b, int logT) {
+  if (pass == 2) return (size_t(1) << logT) * ((size_t(1) << (L2 + b)) + 1);
+  return (size_t(1) << logT) * ((size_t(1) << L1) + 1);
+}
+
+}  // namespace lde
+}  // namespace v3db

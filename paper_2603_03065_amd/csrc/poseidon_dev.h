@@ -1,0 +1,144 @@
+// Device routines of the width-12 Poseidon permutation, shared by the
+// single-trace kernels (poseidon.hip) and the batch kernels (batch.hip).
+//
+// Round r: add round constants to all 12 lanes, x^7 on all lanes (r < 4 or
+// r >= 26) or on lane 0 only, then multiply by the circulant MDS matrix
+// M[i][j] = a[(j - i) mod 12] with small entries a[j] in [1, 255].
+//
+// The state is kept relaxed in [0, 2^64) between rounds and reduced to [0, p)
+// only when written out. The matrix product uses the entries' smallness: each
+// state word is split into 32-bit halves and every output accumulates
+//   lo = sum_j a * s_j.lo,  hi = sum_j a * s_j.hi   (each < 12 * 255 * 2^32 < 2^44)
+// with one v_mad_u64_u32 per term; lo + hi * 2^32 (< 2^77) is then folded with
+// 2^64 = 2^32 - 1 (mod p). The round constants are wave-uniform scalar loads;
+// the 12 matrix entries are kernel arguments (SGPRs).
+#pragma once
+#include "internal.h"
+
+namespace v3db {
+namespace pos {
+
+struct Circ {
+  uint32_t a[WIDTH];
+};
+
+__device__ __forceinline__ uint64_t sbox(uint64_t x) {
+  const uint64_t x2 = gl::mul_r(x, x);
+  const uint64_t x3 = gl::mul_r(x2, x);
+  const uint64_t x4 = gl::mul_r(x2, x2);
+  return gl::mul_r(x3, x4);
+}
+
+// lo + hi * 2^32 for lo, hi < 2^46, to a relaxed value: with hi = hh*2^32 + hl,
+// the sum is lo + hh*2^64 + hl*2^32 = (hh*(2^32-1) + lo) + hl*2^32 (mod p); the
+// first part is one multiply-add below 2^47, the second adds hl to its high word
+// and a carry out of bit 64 is worth 2^32 - 1 again.
+__device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
+  const uint64_t t = (uint64_t)(uint32_t)(hi >> 32) * gl::EPS + lo;
+  const uint32_t th = (uint32_t)(t >> 32);
+  const uint32_t rh = th + (uint32_t)hi;
+  uint64_t r = ((uint64_t)rh << 32) | (uint32_t)t;
+  if (rh < th) r += gl::EPS;
+  return r;
+}
+
+// state <- M * state + rc_next. The next round's constants enter as the initial
+// values of the two accumulators (their low and high 32-bit halves), so the
+// constant addition costs nothing. All sums stay below 2^44.
+__device__ __forceinline__ void mds_ark(uint64_t s[WIDTH], const uint32_t a[WIDTH],
+                                        const uint64_t *__restrict__ rc_next) {
+  uint32_t lo[WIDTH], hi[WIDTH];
+#pragma unroll
+  for (int j = 0; j < WIDTH; j++) {
+    lo[j] = (uint32_t)s[j];
+    hi[j] = (uint32_t)(s[j] >> 32);
+  }
+#pragma unroll
+  for (int i = 0; i < WIDTH; i++) {
+    const uint64_t rc = rc_next[i];
+    uint64_t al = (uint32_t)rc, ah = rc >> 32;
+#pragma unroll
+    for (int j = 0; j < WIDTH; j++) {
+      const uint32_t c = a[(j - i + WIDTH) % WIDTH];
+      al += (uint64_t)c * lo[j];
+      ah += (uint64_t)c * hi[j];
+    }
+    s[i] = fold(al, ah);
+  }
+}
+
+// The matrix entries as per-lane registers: with the multiplier in a VGPR, the
+// accumulator's initial value (a round constant in SGPRs) can be the
+// multiply-add's scalar operand.
+__device__ __forceinline__ void circ_to_vgprs(const Circ &c, uint32_t a[WIDTH]) {
+#pragma unroll
+  for (int i = 0; i < WIDTH; i++) asm volatile("v_mov_b32 %0, %1" : "=v"(a[i]) : "s"(c.a[i]));
+}
+
+// rc: 31 rows of 12 (the 30 rounds' constants, then a row of zeros so the last
+// round's linear layer can take "next constants" like every other round).
+__device__ __forceinline__ void permute(uint64_t s[WIDTH], const uint64_t *__restrict__ rc, const uint32_t a[WIDTH]) {
+#pragma unroll
+  for (int i = 0; i < WIDTH; i++) s[i] = gl::add_r(s[i], rc[i]);
+#pragma unroll 1
+  for (int r = 0; r < FULL_HALF; r++) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
+#pragma unroll 1
+  for (int r = FULL_HALF; r < ROUNDS - FULL_HALF; r++) {
+    s[0] = sbox(s[0]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
+#pragma unroll 1
+  for (int r = ROUNDS - FULL_HALF; r < ROUNDS; r++) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+    mds_ark(s, a, rc + (r + 1) * WIDTH);
+  }
+}
+
+// Leaf digest of row k of a column-major matrix with n_rows rows: the rate-8
+// overwrite sponge over columns 0..n_cols-1 (lane k reads column c at row k, so a
+// wave's loads are 64 consecutive words of one column). Writes 4 canonical words.
+__device__ __forceinline__ void leaf_digest(const uint64_t *__restrict__ mat, uint32_t n_cols, uint64_t n_rows,
+                                            uint64_t k, uint64_t *__restrict__ out, const uint64_t *__restrict__ rc,
+                                            const uint32_t a[WIDTH]) {
+  uint64_t s[WIDTH];
+#pragma unroll
+  for (int i = 0; i < WIDTH; i++) s[i] = 0;
+  for (uint32_t q = 0; q < n_cols; q += RATE) {
+    const uint32_t len = (n_cols - q) < RATE ? (n_cols - q) : RATE;
+    const uint64_t *base = mat + uint64_t(q) * n_rows + k;
+#pragma unroll
+    for (int i = 0; i < RATE; i++)
+      if (i < (int)len) s[i] = base[uint64_t(i) * n_rows];
+    permute(s, rc, a);
+  }
+#pragma unroll
+  for (int i = 0; i < DIGEST; i++) out[i] = gl::canon(s[i]);
+}
+
+// Node k of a level = Compress(below[2k], below[2k+1]).
+__device__ __forceinline__ void merkle_node(const uint64_t *__restrict__ below, uint64_t k, uint64_t *__restrict__ out,
+                                            const uint64_t *__restrict__ rc, const uint32_t a[WIDTH]) {
+  uint64_t s[WIDTH];
+  const uint64_t *src = below + k * (2 * DIGEST);
+#pragma unroll
+  for (int i = 0; i < 2 * DIGEST; i++) s[i] = src[i];
+#pragma unroll
+  for (int i = 2 * DIGEST; i < WIDTH; i++) s[i] = 0;
+  permute(s, rc, a);
+#pragma unroll
+  for (int i = 0; i < DIGEST; i++) out[i] = gl::canon(s[i]);
+}
+
+inline Circ circ_of(const v3db_ctx *ctx) {
+  Circ c;
+  for (int i = 0; i < WIDTH; i++) c.a[i] = ctx->pos.circ[i];
+  return c;
+}
+
+}  // namespace pos
+}  // namespace v3db

@@ -63,11 +63,17 @@ def test_scratch_size_is_host_logic(v3db):
     jobs[0] = J(None, 8, 12, 3, 0, 7, 0, None, None, None)
     jobs[1] = J(None, 80, 10, 3, 2, 7, 0, None, None, None)
     b = lib.v3db_commit_batch_scratch_bytes(jobs, 2)
-    # LDE 80 * 2^13 * 8 plus max(Z for 8 columns, tree (2^14 - 4) digests)
-    lde = 80 * (1 << 13) * 8
-    z = 8 * (1 << 13) * 8
-    tree = ((1 << 14) - 4) * 32
-    assert b == max(8 * (1 << 15) * 8 + max(8 * (1 << 15) * 8, ((1 << 16) - 1) * 32), lde + max(z, tree))
+    # two natural-layout jobs are batched: Y (n words per column), LDE and tree of
+    # every job coexist, each rounded up to 256 bytes
+    def batched(C, L, h):
+        y = C * (1 << L) * 8
+        lde = C * (1 << (L + 3)) * 8
+        tree = ((2 << (L + 3)) - (1 << h)) * 32
+        return (y + lde + tree + 255) // 256 * 256
+    assert b == batched(8, 12, 0) + batched(80, 10, 2)
+    # a lone job is committed alone: its LDE, then a region shared by Y and the tree
+    one = lib.v3db_commit_batch_scratch_bytes(jobs, 1)
+    assert one == 8 * (1 << 15) * 8 + max(8 * (1 << 12) * 8, ((2 << 15) - 1) * 32)
 
 
 def test_null_context_is_rejected_without_device(v3db):
