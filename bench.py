@@ -57,7 +57,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + [BATCH_WORKLOAD])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, "serve-poisson"])
+    ap.add_argument("--serve-seconds", type=float, default=120.0)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=16)
+    ap.add_argument("--serve-saturation", type=int, default=300, help="requests queued at once for saturation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
                     help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
@@ -144,6 +150,123 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+SERVE_WORKLOAD = "serve-poisson"
+
+
+def serve_requests(seconds, rate):
+    """Seeded open-loop arrivals: exponential gaps (rate per second) from
+    SplitMix64 stream 0x56340005; a request is 80 cols x 2^18 rows (cap height 4)
+    with probability 0.05 (stream 0x56340105), else drawn from the batch
+    workload's distribution (stream 0x56340205: log rows 10..18, cols 20..135,
+    cap height 2)."""
+    import math as m
+    from paper_2603_03065_amd import inputs
+    out, t, i = [], 0.0, 0
+    while True:
+        u = float(inputs.uniform01(0x56340005, i))
+        t += -m.log(1.0 - u) / rate
+        if t >= seconds:
+            return out
+        big = float(inputs.uniform01(0x56340105, i)) < 0.05
+        if big:
+            L, C, h = 18, 80, 4
+        else:
+            L = 10 + int(inputs.splitmix64(0x56340205, 2 * i)) % 9
+            C = 20 + int(inputs.splitmix64(0x56340205, 2 * i + 1)) % 116
+            h = 2
+        out.append((t, L, C, h))
+        i += 1
+
+
+def serve_main(args):
+    """Open-loop Poisson arrivals into the continuous-batching server, then the
+    same arrivals into a one-request-at-a-time FIFO server; plus saturation
+    throughput of both with every request queued at once."""
+    import numpy as np
+    import torch
+
+    import paper_2603_03065_amd as v3db
+    from paper_2603_03065_amd import inputs
+
+    reqs = serve_requests(args.serve_seconds, args.serve_rate)
+    host = torch.from_numpy(inputs.trace(5, 0, 135, 18).reshape(-1).view(np.int64)).pin_memory()
+    ctx = v3db.Context(0)
+
+    def run(slots, max_batch, arrivals, open_loop):
+        srv = v3db.Server(ctx, slots=slots, hbm_budget=64 << 30, max_batch=max_batch)
+        # warm the pool and the kernels
+        for L, C, h in {(18, 80, 4), (14, 60, 2)}:
+            srv.submit(host, cap_height=h, shape=(C, L))
+        srv.drain()
+        t0 = v3db.clock() + 0.05
+        tickets = []
+        next_note = 10.0
+        for (t, L, C, h) in arrivals:
+            if open_loop and t >= next_note:
+                print(f"serve: slots={slots} max_batch={max_batch} t={t:.0f}s submitted={len(tickets)}",
+                      file=sys.stderr, flush=True)
+                next_note += 10.0
+            target = t0 + (t if open_loop else 0.0)
+            while open_loop and v3db.clock() < target:
+                time.sleep(min(0.002, max(0.0, target - v3db.clock())))
+            tickets.append((srv.submit(host, cap_height=h, shape=(C, L), t_arrive=target), t, L, C))
+        srv.drain()
+        rows = []
+        for tk, t, L, C in tickets:
+            st, cap, tm = srv.poll(tk)
+            assert st == 0
+            rows.append((t, C << (L + 3), tm["t_done"] - tm["t_arrive"], tm["t_done"] - t0, tm["batch_size"]))
+        stats = srv.stats()
+        srv.close()
+        return rows, stats
+
+    def summarize(rows, warm):
+        sel = [r for r in rows if r[0] >= warm]
+        lat = np.array([r[2] for r in sel]) * 1e3
+        elems = sum(r[1] for r in sel)
+        span = max(r[3] for r in sel) - warm
+        return {"requests": len(sel), "throughput_lde_elems_per_s": elems / span,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_batch": float(np.mean([r[4] for r in sel]))}
+
+    warm = min(10.0, args.serve_seconds / 4)
+    cb_rows, cb_stats = run(args.serve_slots, args.serve_max_batch, reqs, True)
+    print("serve: continuous batching done", file=sys.stderr, flush=True)
+    fifo_rows, _ = run(1, 1, reqs, True)
+    print("serve: fifo done", file=sys.stderr, flush=True)
+    sat = reqs[: args.serve_saturation]
+    sat_cb, _ = run(args.serve_slots, args.serve_max_batch, sat, False)
+    sat_fifo, _ = run(1, 1, sat, False)
+    print("serve: saturation done", file=sys.stderr, flush=True)
+    sat_elems = sum(r[1] for r in sat_cb)
+    cb = summarize(cb_rows, warm)
+    fifo = summarize(fifo_rows, warm)
+    out = {
+        "metric": METRIC,
+        "value": cb["throughput_lde_elems_per_s"],
+        "unit": "LDE field elems/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{SERVE_WORKLOAD}: Poisson {args.serve_rate}/s for {args.serve_seconds}s, 95% batch-mix "
+                               "jobs (log rows 10..18, cols 20..135, cap 2) + 5% 80x2^18 jobs (cap 4), blowup 8, "
+                               f"64 GiB admission budget, {args.serve_slots} slots, max batch {args.serve_max_batch}; "
+                               f"stats over arrivals after {warm:.0f}s; latency from arrival stamp to cap on host "
+                               "including trace upload from pinned memory",
+                   "requests": len(reqs)},
+        "latency_ms": {"p50": cb["p50_ms"], "p99": cb["p99_ms"]},
+        "continuous_batching": cb,
+        "fifo_one_at_a_time": fifo,
+        "saturation": {"requests": len(sat),
+                       "continuous_batching_lde_elems_per_s": sat_elems / max(r[3] for r in sat_cb),
+                       "fifo_lde_elems_per_s": sat_elems / max(r[3] for r in sat_fifo)},
+        "server_stats": cb_stats,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -152,6 +275,8 @@ def main():
         sys.exit(2)
     if args.workload == BATCH_WORKLOAD:
         return batch_main(args)
+    if args.workload == SERVE_WORKLOAD:
+        return serve_main(args)
 
     import numpy as np
     import torch

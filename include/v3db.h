@@ -36,9 +36,9 @@
  *   - The caller owns every buffer. Calls validate arguments on the host, enqueue
  *     work on `stream` (a hipStream_t; NULL = the default stream) and return;
  *     buffers must stay alive until the stream reaches that point.
- *   - A context is used from one host thread at a time (the server API below is
- *     the exception). Calls on one context that share its scratch must not
- *     overlap on different streams; see v3db_commit_batch.
+ *   - A context is used from one host thread at a time; a server owns its context
+ *     while it runs (it calls it from its scheduler thread). Scratch is kept per
+ *     stream, so calls on different streams may overlap.
  *   - Errors are returned as v3db_status; v3db_last_error() gives a message for
  *     the last failing call on the calling thread. No exception crosses the ABI.
  */
@@ -177,6 +177,66 @@ v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value);
 
 /* Device bytes of scratch a batch of jobs needs beyond the caller's buffers. */
 size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs);
+
+/* ---------------------------------------------------------------- serving
+ * An audit-on-demand commit server: requests (host traces) arrive at any time;
+ * a scheduler thread admits them in arrival order whenever a slot (a stream) and
+ * enough of the server's HBM budget are free, as many as fit into one batch, and
+ * runs each batch on its slot stream: trace upload, one v3db_commit_batch, cap
+ * download. Batches on different slots overlap on the device; a request that
+ * arrives while others run is admitted as soon as a slot and memory free up.
+ * All request buffers (trace, LDE, tree, cap) and batch scratch live in one
+ * device arena of the budget's size, reserved at creation and kept resident;
+ * a request is admitted when its buffers fit in the arena. */
+typedef struct {
+  uint32_t slots;             /* batches in flight at once (streams), >= 1 */
+  uint32_t max_batch;         /* requests per batch, 0 = no limit */
+  uint32_t max_queue;         /* queued requests before submit returns BUSY, 0 = no limit */
+  size_t hbm_budget_bytes;    /* device memory for request buffers: trace, LDE, tree, Y scratch */
+  double sim_ns_per_element;  /* > 0: no device work, each batch "runs" for this many ns per
+                                 LDE element (tests of the scheduler without a GPU; ctx may be NULL) */
+} v3db_server_cfg;
+
+#define V3DB_REQ_FAIL_INJECT 1u /* test hook: the request fails at admission, others are unaffected */
+
+typedef struct {
+  const uint64_t *h_trace;    /* host [n_cols][2^log_rows], canonical; pinned memory lets the upload
+                                 overlap; must stay valid until the request is done */
+  uint32_t n_cols, log_rows, log_blowup, cap_height;
+  uint64_t shift;
+  uint64_t *h_cap;            /* host [2^cap_height][4], written when the request is done */
+  double t_arrive;            /* arrival stamp on v3db_clock(); < 0 means "now" */
+  uint32_t flags;
+} v3db_request;
+
+typedef struct {
+  double t_arrive, t_admit, t_done; /* v3db_clock() seconds; latency = t_done - t_arrive */
+  uint32_t batch_size;              /* requests in the batch it ran in */
+  uint32_t slot;
+} v3db_request_timing;
+
+typedef struct {
+  uint64_t submitted, completed, failed, batches;
+  size_t hbm_in_use, hbm_peak;      /* bytes of admitted requests now / at most */
+  size_t pool_bytes;                /* device memory held by the server (its arena: the budget) */
+} v3db_server_stats;
+
+/* Seconds on a monotonic clock (the one request stamps use). */
+double v3db_clock(void);
+/* ctx may be NULL only when cfg->sim_ns_per_element > 0. Errors: INVALID_ARG. */
+v3db_status v3db_server_create(v3db_ctx *ctx, const v3db_server_cfg *cfg, v3db_server **out);
+/* Queue a request; *ticket identifies it. Errors: INVALID_ARG / UNSUPPORTED (as for a
+ * commit job), OUT_OF_MEMORY (its buffers alone exceed the budget), BUSY (queue full). */
+v3db_status v3db_server_submit(v3db_server *srv, const v3db_request *req, uint64_t *ticket);
+/* *done = 1 once the request finished (its h_cap written, or an error in *status);
+ * a finished ticket is forgotten after this call reports it. */
+v3db_status v3db_server_poll(v3db_server *srv, uint64_t ticket, int *done, v3db_status *status,
+                             v3db_request_timing *timing);
+/* Block until every request submitted so far has finished. */
+v3db_status v3db_server_drain(v3db_server *srv);
+v3db_status v3db_server_stats_get(v3db_server *srv, v3db_server_stats *out);
+/* Drains, stops the scheduler and frees the pool. */
+void v3db_server_destroy(v3db_server *srv);
 
 #ifdef __cplusplus
 }

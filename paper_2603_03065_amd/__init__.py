@@ -53,6 +53,52 @@ class _Job(ctypes.Structure):
     ]
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint32),
+        ("max_queue", ctypes.c_uint32),
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("sim_ns_per_element", ctypes.c_double),
+    ]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [
+        ("h_trace", ctypes.c_void_p),
+        ("n_cols", ctypes.c_uint32),
+        ("log_rows", ctypes.c_uint32),
+        ("log_blowup", ctypes.c_uint32),
+        ("cap_height", ctypes.c_uint32),
+        ("shift", ctypes.c_uint64),
+        ("h_cap", ctypes.c_void_p),
+        ("t_arrive", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [
+        ("t_arrive", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("batch_size", ctypes.c_uint32),
+        ("slot", ctypes.c_uint32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64),
+        ("hbm_in_use", ctypes.c_size_t),
+        ("hbm_peak", ctypes.c_size_t),
+        ("pool_bytes", ctypes.c_size_t),
+    ]
+
+
 _lib = None
 
 
@@ -80,6 +126,13 @@ def lib():
         "v3db_commit_batch_scratch_bytes": (sz, [ctypes.POINTER(_Job), sz]),
         "v3db_profile_enable": (i32, [vp, i32]),
         "v3db_set_option": (i32, [vp, i32, u64]),
+        "v3db_clock": (ctypes.c_double, []),
+        "v3db_server_create": (i32, [vp, ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]),
+        "v3db_server_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(u64)]),
+        "v3db_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(_Timing)]),
+        "v3db_server_drain": (i32, [vp]),
+        "v3db_server_stats_get": (i32, [vp, ctypes.POINTER(_Stats)]),
+        "v3db_server_destroy": (None, [vp]),
         "v3db_profile_read": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -257,3 +310,82 @@ class Context:
 def commit_batch_scratch_bytes(jobs: Sequence[Job]) -> int:
     arr = Context._jobs(jobs)
     return int(lib().v3db_commit_batch_scratch_bytes(arr, len(jobs)))
+
+
+REQ_FAIL_INJECT = 1
+
+
+def clock() -> float:
+    """Seconds on the monotonic clock the server stamps requests with."""
+    return float(lib().v3db_clock())
+
+
+class Server:
+    """Continuous-batching commit server (see v3db_server_* in include/v3db.h).
+
+    submit() takes a host trace (a contiguous uint64 numpy array or an int64 CPU
+    tensor, ideally pinned) and returns a ticket; the caller keeps the trace alive
+    until the request is done. Results land in a per-request host cap array.
+    """
+
+    def __init__(self, ctx: Optional[Context], slots: int = 4, hbm_budget: int = 64 << 30, max_batch: int = 0,
+                 max_queue: int = 0, sim_ns_per_element: float = 0.0):
+        cfg = _ServerCfg(slots, max_batch, max_queue, hbm_budget, sim_ns_per_element)
+        h = ctypes.c_void_p()
+        _check(lib().v3db_server_create(ctx.handle if ctx is not None else None, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._keep = {}
+
+    def submit(self, trace, log_blowup: int = 3, cap_height: int = 2, shift: int = 7, t_arrive: float = -1.0,
+               flags: int = 0, shape=None):
+        """trace: host [n_cols][2^log_rows] (uint64 numpy or int64 CPU tensor), or with shape=(n_cols,
+        log_rows) any object exposing a data pointer via .ctypes.data / .data_ptr() of that many words."""
+        if shape is None:
+            n_cols, n = trace.shape
+            log_rows = int(n).bit_length() - 1
+        else:
+            n_cols, log_rows = shape
+        ptr = trace.data_ptr() if hasattr(trace, "data_ptr") else trace.ctypes.data
+        cap = np.zeros((1 << cap_height, 4), dtype=np.uint64)
+        req = _Request(ptr, n_cols, log_rows, log_blowup, cap_height, shift, cap.ctypes.data, t_arrive, flags)
+        ticket = ctypes.c_uint64(0)
+        _check(lib().v3db_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket)))
+        self._keep[int(ticket.value)] = (trace, cap)
+        return int(ticket.value)
+
+    def poll(self, ticket: int):
+        """None while running; else (status, cap, timing dict)."""
+        done, st, t = ctypes.c_int(0), ctypes.c_int(0), _Timing()
+        _check(lib().v3db_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(t)))
+        if not done.value:
+            return None
+        _, cap = self._keep.pop(ticket)
+        timing = {"t_arrive": t.t_arrive, "t_admit": t.t_admit, "t_done": t.t_done,
+                  "batch_size": int(t.batch_size), "slot": int(t.slot)}
+        return int(st.value), cap, timing
+
+    def drain(self):
+        _check(lib().v3db_server_drain(self._h))
+
+    def stats(self):
+        s = _Stats()
+        _check(lib().v3db_server_stats_get(self._h, ctypes.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in _Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().v3db_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -435,6 +435,13 @@ size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_job
 }
 
 v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, v3db_stream stream) {
+  return v3db::commit_batch_impl(ctx, jobs, n_jobs, (hipStream_t)stream, nullptr, 0);
+}
+
+}  // extern "C"
+
+v3db_status v3db::commit_batch_impl(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, hipStream_t s,
+                                    void *scratch_in, size_t scratch_bytes) {
   clear_error();
   if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "commit_batch: NULL ctx");
   if (n_jobs == 0) return V3DB_OK;
@@ -445,7 +452,6 @@ v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t
   }
   std::lock_guard<std::mutex> g(ctx->mu);
   (void)hipSetDevice(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
   // Natural-layout jobs go through the batched graph, in groups whose scratch
   // stays within the group cap; the others (and every job when batching is
   // switched off) are committed one at a time.
@@ -476,9 +482,14 @@ v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t
     for (const auto &j : gr) b += batched_scratch(j);
     need = std::max(need, b);
   }
-  void *scratch = nullptr;
-  v3db_status st = ctx_scratch(ctx, s, need, &scratch);
-  if (st != V3DB_OK) return st;
+  void *scratch = scratch_in;
+  v3db_status st = V3DB_OK;
+  if (scratch) {
+    if (scratch_bytes < need) return set_error(V3DB_ERR_INVALID_ARG, "commit_batch: scratch too small");
+  } else {
+    st = ctx_scratch(ctx, s, need, &scratch);
+    if (st != V3DB_OK) return st;
+  }
   for (const auto &gr : groups) {
     st = commit_group(ctx, gr, (uint8_t *)scratch, s);
     if (st != V3DB_OK) return st;
@@ -489,5 +500,3 @@ v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t
   }
   return V3DB_OK;
 }
-
-}  // extern "C"

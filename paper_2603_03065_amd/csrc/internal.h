@@ -111,8 +111,11 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
 hipEvent_t prof_mark(v3db_ctx *ctx, hipStream_t stream);
 void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 
-// Batched commits (batch.hip).
+// Batched commits (batch.hip). scratch (nullable) replaces the context's
+// per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+v3db_status commit_batch_impl(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, hipStream_t stream,
+                              void *scratch, size_t scratch_bytes);
 
 // Poseidon work (poseidon.hip).
 v3db_status enqueue_permute(v3db_ctx *ctx, uint64_t *states, size_t count, hipStream_t stream);
