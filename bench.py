@@ -52,6 +52,25 @@ OPS_PER_PERMUTATION = 472 * 10 + 4320 * 2 + 360 * 3 + 360 * 6
 LDE_BYTES_PER_ELEMENT = 9
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
+    kernel's sources changed since the counters were taken or no run covers this workload."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["source_digest"] or rec["workload"] != workload:
+        return None
+    return rec["hbm_bytes_per_dispatch"]
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +84,8 @@ def parse():
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests queued at once for saturation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device 3 times (reference for the HBM byte counters)")
     ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
                     help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
     return ap.parse_args()
@@ -273,6 +294,15 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_per_copy": src.numel() * 8, "copies": 3}}), flush=True)
+        return
     if args.workload == BATCH_WORKLOAD:
         return batch_main(args)
     if args.workload == SERVE_WORKLOAD:
@@ -359,7 +389,8 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "Tops/s (32-bit integer VALU lane-ops)",
             "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": measured_traffic("k_leaf_hash", args.workload),
+            "algorithmic_bytes": elems * 8 + N * 32,
             "ops_per_launch": perms_leaf * OPS_PER_PERMUTATION,
             "avg_launch_ms": leaf_avg_s * 1e3,
         },
