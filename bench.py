@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-saturation", type=int, default=300, help="requests queued at once for saturation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default LDE schedules instead of tuning them before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (reference for the HBM byte counters)")
     ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
@@ -109,6 +111,11 @@ def cpu_baseline(n_cols, log_blowup, cap_height, layout, log_rows):
     }
 
 
+def schedule_json(s):
+    return {"split_log": s.split_log, "tile_cap": list(s.tile_cap), "chunk_cols": s.chunk_cols,
+            "tuned_lde_us": s.time_us}
+
+
 def batch_main(args):
     """64 traces of mixed shapes committed by one v3db_commit_batch call (batched
     phase launches replayed from a HIP graph), against the same jobs committed
@@ -132,6 +139,11 @@ def batch_main(args):
                              tree=torch.empty((2 * N - 4, 4), dtype=torch.int64, device=dev)))
         elems += C * N
     stream = torch.cuda.current_stream(dev)
+    tuned = {}
+    if not args.no_autotune:  # one schedule per extension shape, tuned before any timing
+        for L in sorted(set(L for L, _ in shapes)):
+            C = int(np.median([c for l2, c in shapes if l2 == L]))
+            tuned[L] = schedule_json(ctx.autotune_lde(L, 3, C, 0))
 
     def run(batching, steps, warmup):
         ctx.set_batching(batching)
@@ -162,6 +174,7 @@ def batch_main(args):
                                "20..135, blowup 8, cap height 2, natural layout, one v3db_commit_batch call",
                    "lde_elements_per_step": elems,
                    "shapes": [[L, C] for L, C in shapes]},
+        "lde_schedules": tuned or "default",
         "latency_ms": {"p50": float(np.percentile(ms_b, 50)), "p99": float(np.percentile(ms_b, 99))},
         "one_launch_per_trace": {"value": elems * len(ms_s) / wall_s, "ms_per_step": wall_s * 1e3 / len(ms_s),
                                  "p50_ms": float(np.percentile(ms_s, 50))},
@@ -326,6 +339,8 @@ def main():
     cap = torch.empty((1 << h, 4), dtype=torch.int64, device=dev)
     job = v3db.Job(trace=trace, log_blowup=b, cap_height=h, shift=7, layout=layout, lde=lde, tree=tree, cap=cap)
     stream = torch.cuda.current_stream(dev)
+    default_schedule = schedule_json(ctx.get_schedule(L, b))
+    schedule = default_schedule if args.no_autotune else schedule_json(ctx.autotune_lde(L, b, C, layout))
 
     for _ in range(args.warmup):
         ctx.commit(job, stream)
@@ -382,6 +397,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "min": float(step_ms.min()), "max": float(step_ms.max())},
         "trace_elements_per_s": C * n * args.steps / wall,
+        "lde_schedule": {"used": schedule, "default": default_schedule,
+                         "autotuned": not args.no_autotune},
         "roofline": {
             "kernel": "k_leaf_hash (rate-8 Poseidon sponge over every extended row)",
             "bound": "alu",

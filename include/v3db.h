@@ -175,6 +175,58 @@ v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out
 typedef enum { V3DB_OPT_BATCHING = 0, V3DB_OPT_BATCH_GROUP_BYTES = 1 } v3db_option;
 v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value);
 
+/* ---------------------------------------------------------------- schedules
+ * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
+ * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):
+ * pass 1 runs inverse size-n1 sub-transforms in tiles of 2^t1 columns, pass 2 the
+ * inverse size-n2 and forward size-(B n2) transforms in tiles of 2^t2 rows, pass 3
+ * the forward size-n1 transforms in tiles of 2^t3 columns; the single-trace path
+ * runs passes 2 and 3 over chunk_cols columns at a time. A schedule never changes
+ * results, only speed. Every context starts with a default schedule for each shape;
+ * v3db_autotune_lde times candidates on the device and installs the fastest.
+ *   split_log   log2 n2: n1 = 2^(log_rows - split_log) <= 4096, n2 <= 4096,
+ *               split_log + log_blowup <= 14
+ *   tile_cap[k] upper bound on log2 of pass k+1's tile height, 0..4 (the height is
+ *               also bounded by LDS: 2^t * M <= 8192 words for transform length M)
+ *   chunk_cols  1..16
+ *   time_us     the extension's measured time when the schedule was tuned (0 if
+ *               never timed); informational. */
+typedef struct {
+  uint32_t log_rows, log_blowup;
+  uint32_t split_log;
+  uint32_t tile_cap[3];
+  uint32_t chunk_cols;
+  double time_us;
+} v3db_schedule;
+
+/* Time candidate schedules for one shape and install the fastest in the context
+ * (coordinate search from the current default: the split, each pass's tile cap,
+ * the column chunk). Runs an LDE of n_cols synthetic columns in the given layout
+ * several times per candidate on a private stream, allocating its buffers from the
+ * context budget for the duration of the call; blocks until done. The context's
+ * cached tables and batched graphs for the shape are dropped. out may be NULL.
+ * Errors: INVALID_ARG / UNSUPPORTED for shapes v3db_lde rejects, OUT_OF_MEMORY,
+ * HIP. Must not overlap any other call on the context (it waits for the device). */
+v3db_status v3db_autotune_lde(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint32_t n_cols,
+                              v3db_layout layout, v3db_schedule *out);
+
+/* The schedule the context uses for a shape (the default one if none was set). */
+v3db_status v3db_get_schedule(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, v3db_schedule *out);
+
+/* Install a schedule for (s->log_rows, s->log_blowup); INVALID_ARG if it breaks
+ * the bounds above. Drops the shape's cached tables and the batched graphs, so
+ * it waits for the device first. */
+v3db_status v3db_set_schedule(v3db_ctx *ctx, const v3db_schedule *s);
+
+/* Save every installed (set or tuned) schedule as text, one line per shape:
+ *   "v3db-schedule <log_rows> <log_blowup> <split_log> <cap1> <cap2> <cap3> <chunk> <time_us>"
+ * and load such a file back (lines that do not start with "v3db-schedule" are
+ * ignored; a malformed or out-of-bounds schedule line fails the load with
+ * INVALID_ARG, leaving the schedules installed before it in place). The count of
+ * schedules written / read goes to *count (may be NULL). IO errors: INVALID_ARG. */
+v3db_status v3db_schedules_save(v3db_ctx *ctx, const char *path, size_t *count);
+v3db_status v3db_schedules_load(v3db_ctx *ctx, const char *path, size_t *count);
+
 /* Device bytes of scratch a batch of jobs needs beyond the caller's buffers. */
 size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs);
 

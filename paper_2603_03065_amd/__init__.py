@@ -99,6 +99,36 @@ class _Stats(ctypes.Structure):
     ]
 
 
+class _Schedule(ctypes.Structure):
+    _fields_ = [
+        ("log_rows", ctypes.c_uint32),
+        ("log_blowup", ctypes.c_uint32),
+        ("split_log", ctypes.c_uint32),
+        ("tile_cap", ctypes.c_uint32 * 3),
+        ("chunk_cols", ctypes.c_uint32),
+        ("time_us", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Schedule:
+    """How one (log_rows, log_blowup) extension is cut into kernels (see v3db_schedule)."""
+    log_rows: int
+    log_blowup: int
+    split_log: int
+    tile_cap: tuple
+    chunk_cols: int
+    time_us: float = 0.0
+
+    @staticmethod
+    def _from(c: "_Schedule") -> "Schedule":
+        return Schedule(c.log_rows, c.log_blowup, c.split_log, tuple(c.tile_cap), c.chunk_cols, c.time_us)
+
+    def _to(self) -> "_Schedule":
+        return _Schedule(self.log_rows, self.log_blowup, self.split_log, (ctypes.c_uint32 * 3)(*self.tile_cap),
+                         self.chunk_cols, self.time_us)
+
+
 _lib = None
 
 
@@ -134,6 +164,11 @@ def lib():
         "v3db_server_stats_get": (i32, [vp, ctypes.POINTER(_Stats)]),
         "v3db_server_destroy": (None, [vp]),
         "v3db_profile_read": (i32, [vp, vp, vp]),
+        "v3db_autotune_lde": (i32, [vp, u32, u32, u32, i32, ctypes.POINTER(_Schedule)]),
+        "v3db_get_schedule": (i32, [vp, u32, u32, ctypes.POINTER(_Schedule)]),
+        "v3db_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
+        "v3db_schedules_save": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(sz)]),
+        "v3db_schedules_load": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(sz)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -305,6 +340,31 @@ class Context:
 
     def commit(self, job: Job, stream=None):
         return self.commit_batch([job], stream)[0]
+
+    def autotune_lde(self, log_rows: int, log_blowup: int, n_cols: int, layout: int = NATURAL) -> Schedule:
+        """Time candidate schedules for the shape on the device and install the fastest."""
+        out = _Schedule()
+        _check(lib().v3db_autotune_lde(self._h, log_rows, log_blowup, n_cols, layout, ctypes.byref(out)))
+        return Schedule._from(out)
+
+    def get_schedule(self, log_rows: int, log_blowup: int) -> Schedule:
+        out = _Schedule()
+        _check(lib().v3db_get_schedule(self._h, log_rows, log_blowup, ctypes.byref(out)))
+        return Schedule._from(out)
+
+    def set_schedule(self, s: Schedule):
+        c = s._to()
+        _check(lib().v3db_set_schedule(self._h, ctypes.byref(c)))
+
+    def save_schedules(self, path: str) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().v3db_schedules_save(self._h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
+    def load_schedules(self, path: str) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().v3db_schedules_load(self._h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
 
 
 def commit_batch_scratch_bytes(jobs: Sequence[Job]) -> int:

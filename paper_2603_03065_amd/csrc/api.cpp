@@ -1,5 +1,6 @@
 // C-ABI entry points: context, errors, argument checks, scratch, and the
 // single-trace calls. The batched path lives in batch.hip.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -334,6 +335,138 @@ v3db_status v3db_merkle_commit(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_
   st = enqueue_leaf_hash(ctx, d_mat, n_cols, log_leaves, tree, s);
   if (st != V3DB_OK) return st;
   return enqueue_merkle_levels(ctx, tree, log_leaves, cap_height, d_cap, s);
+}
+
+
+static v3db::LdeSchedule to_internal(const v3db_schedule &s) {
+  v3db::LdeSchedule r{};
+  r.L2 = s.split_log;
+  r.cap1 = s.tile_cap[0], r.cap2 = s.tile_cap[1], r.cap3 = s.tile_cap[2];
+  r.chunk = s.chunk_cols;
+  r.us = s.time_us;
+  return r;
+}
+
+static v3db_schedule to_public(uint32_t L, uint32_t b, const v3db::LdeSchedule &s) {
+  v3db_schedule r{};
+  r.log_rows = L, r.log_blowup = b;
+  r.split_log = s.L2;
+  r.tile_cap[0] = s.cap1, r.tile_cap[1] = s.cap2, r.tile_cap[2] = s.cap3;
+  r.chunk_cols = s.chunk;
+  r.time_us = s.us;
+  return r;
+}
+
+static v3db_status check_shape(const char *who, uint32_t L, uint32_t b) {
+  if (L > V3DB_MAX_LOG_ROWS || b > V3DB_MAX_LOG_BLOWUP || L + b > V3DB_MAX_LOG_LDE)
+    return set_error(V3DB_ERR_UNSUPPORTED, std::string(who) + ": shape beyond the build limits");
+  return V3DB_OK;
+}
+
+// Install a schedule; the caller holds ctx->mu. Cached plans of the shape and every
+// batched graph (which hold the plans' tables and launch shapes) are dropped.
+static v3db_status install_schedule(v3db_ctx *ctx, uint32_t L, uint32_t b, const v3db::LdeSchedule &s) {
+  (void)hipSetDevice(ctx->device);
+  v3db_status st = hip_check(hipDeviceSynchronize(), "set_schedule: wait for device");
+  if (st != V3DB_OK) return st;
+  free_batch_graphs(ctx);
+  drop_plans(ctx, L, b);
+  ctx->tuned[{L, b}] = s;
+  return V3DB_OK;
+}
+
+v3db_status v3db_autotune_lde(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint32_t n_cols,
+                              v3db_layout layout, v3db_schedule *out) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "autotune_lde: NULL ctx");
+  if (n_cols == 0 || n_cols > V3DB_MAX_COLS) return set_error(V3DB_ERR_INVALID_ARG, "autotune_lde: bad n_cols");
+  if (layout != V3DB_LAYOUT_NATURAL && layout != V3DB_LAYOUT_BITREV)
+    return set_error(V3DB_ERR_INVALID_ARG, "autotune_lde: unknown layout");
+  v3db_status st = check_shape("autotune_lde", log_rows, log_blowup);
+  if (st != V3DB_OK) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  v3db::LdeSchedule best;
+  st = autotune_lde(ctx, log_rows, log_blowup, n_cols, layout, &best);
+  if (st != V3DB_OK) return st;
+  st = install_schedule(ctx, log_rows, log_blowup, best);
+  if (st == V3DB_OK && out) *out = to_public(log_rows, log_blowup, best);
+  return st;
+}
+
+v3db_status v3db_get_schedule(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, v3db_schedule *out) {
+  clear_error();
+  if (!ctx || !out) return set_error(V3DB_ERR_INVALID_ARG, "get_schedule: NULL argument");
+  v3db_status st = check_shape("get_schedule", log_rows, log_blowup);
+  if (st != V3DB_OK) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->tuned.find({log_rows, log_blowup});
+  *out = to_public(log_rows, log_blowup,
+                   it != ctx->tuned.end() ? it->second : default_schedule(log_rows, log_blowup));
+  return V3DB_OK;
+}
+
+v3db_status v3db_set_schedule(v3db_ctx *ctx, const v3db_schedule *s) {
+  clear_error();
+  if (!ctx || !s) return set_error(V3DB_ERR_INVALID_ARG, "set_schedule: NULL argument");
+  v3db_status st = check_shape("set_schedule", s->log_rows, s->log_blowup);
+  if (st != V3DB_OK) return st;
+  const v3db::LdeSchedule in = to_internal(*s);
+  if (!schedule_valid(in, s->log_rows, s->log_blowup))
+    return set_error(V3DB_ERR_INVALID_ARG, "set_schedule: schedule out of bounds");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  return install_schedule(ctx, s->log_rows, s->log_blowup, in);
+}
+
+v3db_status v3db_schedules_save(v3db_ctx *ctx, const char *path, size_t *count) {
+  clear_error();
+  if (!ctx || !path) return set_error(V3DB_ERR_INVALID_ARG, "schedules_save: NULL argument");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  FILE *f = fopen(path, "w");
+  if (!f) return set_error(V3DB_ERR_INVALID_ARG, std::string("schedules_save: cannot open ") + path);
+  size_t k = 0;
+  for (const auto &kv : ctx->tuned) {
+    const v3db::LdeSchedule &s = kv.second;
+    fprintf(f, "v3db-schedule %u %u %u %u %u %u %u %.3f\n", kv.first.first, kv.first.second, s.L2, s.cap1,
+            s.cap2, s.cap3, s.chunk, s.us);
+    k++;
+  }
+  const bool ok = fclose(f) == 0;
+  if (!ok) return set_error(V3DB_ERR_INVALID_ARG, std::string("schedules_save: write failed: ") + path);
+  if (count) *count = k;
+  return V3DB_OK;
+}
+
+v3db_status v3db_schedules_load(v3db_ctx *ctx, const char *path, size_t *count) {
+  clear_error();
+  if (!ctx || !path) return set_error(V3DB_ERR_INVALID_ARG, "schedules_load: NULL argument");
+  FILE *f = fopen(path, "r");
+  if (!f) return set_error(V3DB_ERR_INVALID_ARG, std::string("schedules_load: cannot open ") + path);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  char line[256];
+  size_t k = 0, lineno = 0;
+  v3db_status st = V3DB_OK;
+  while (st == V3DB_OK && fgets(line, sizeof line, f)) {
+    lineno++;
+    if (strncmp(line, "v3db-schedule ", 14) != 0) continue;
+    unsigned L, b, l2, c1, c2, c3, ch;
+    double us;
+    v3db::LdeSchedule s{};
+    if (sscanf(line + 14, "%u %u %u %u %u %u %u %lf", &L, &b, &l2, &c1, &c2, &c3, &ch, &us) != 8) {
+      st = set_error(V3DB_ERR_INVALID_ARG, "schedules_load: malformed line " + std::to_string(lineno));
+      break;
+    }
+    s.L2 = l2, s.cap1 = c1, s.cap2 = c2, s.cap3 = c3, s.chunk = ch, s.us = us;
+    if (check_shape("schedules_load", L, b) != V3DB_OK || !schedule_valid(s, L, b)) {
+      st = set_error(V3DB_ERR_INVALID_ARG, "schedules_load: schedule out of bounds on line " + std::to_string(lineno));
+      break;
+    }
+    st = install_schedule(ctx, L, b, s);
+    if (st == V3DB_OK) k++;
+  }
+  fclose(f);
+  if (count) *count = k;
+  return st;
 }
 
 }  // extern "C"

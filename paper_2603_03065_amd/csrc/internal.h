@@ -32,10 +32,19 @@ struct Twiddles {
   uint64_t *dft_fwd, *dft_inv; // w_4096^t and w_4096^-t, t < 4096
 };
 
+// Schedule of the LDE passes for one (log_rows, log_blowup): the split
+// n = n1 * n2 (n2 = 2^L2), caps on each pass's log2 tile height, and how many
+// columns go through passes 2 and 3 together in the single-trace path.
+struct LdeSchedule {
+  uint32_t L2, cap1, cap2, cap3, chunk;
+  double us;  // measured time of the tuning shape (0 = default, untimed)
+};
+
 // Per-shape LDE tables: see ntt.hip.
 struct LdePlan {
   uint32_t log_rows, log_blowup, L1, L2;
   uint32_t logT1, logT2, logT3;  // log2 tile heights of the three passes
+  uint32_t chunk;                // columns per pass-2/3 round (single-trace path)
   uint64_t shift;
   uint64_t *d_twist;  // [B][n2]: (shift^n1 * w_{B n2}^r)^j
   uint64_t *d_scale;  // [n1]: n^-1 * shift^k1
@@ -60,6 +69,7 @@ struct v3db_ctx {
   uint64_t *d_pos = nullptr;  // device copy of pos.rc (flat 360) followed by circ as u64 (12)
   v3db::Twiddles tw{};
   std::map<std::tuple<uint32_t, uint32_t, uint64_t>, v3db::LdePlan> plans;
+  std::map<std::pair<uint32_t, uint32_t>, v3db::LdeSchedule> tuned;  // autotuned schedules
   std::map<void *, v3db::ScratchBuf> scratch;  // per stream
   // phase timing (v3db_profile_*): event pairs per phase, recycled through a pool
   bool profiling = false;
@@ -98,8 +108,15 @@ void free_twiddles(v3db_ctx *ctx);
 v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out);
 
 // Enqueue an LDE (ntt.hip). Arguments already validated.
-// Columns that go through passes 2 and 3 together (their Z stays cache-resident).
+// Columns that go through passes 2 and 3 together (their Z stays cache-resident):
+// the default, and the most a schedule may use (bit-reversed scratch is sized for it).
 constexpr uint32_t LDE_CHUNK_COLS = 8;
+constexpr uint32_t LDE_MAX_CHUNK_COLS = 16;
+LdeSchedule default_schedule(uint32_t log_rows, uint32_t log_blowup);
+void drop_plans(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup);  // frees their tables
+bool schedule_valid(const LdeSchedule &s, uint32_t log_rows, uint32_t log_blowup);
+v3db_status autotune_lde(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint32_t n_cols, v3db_layout layout,
+                         LdeSchedule *out);
 // Scratch of one v3db_lde call: Y (n words per column), plus Z for one chunk of
 // columns in bit-reversed layout (natural layout builds Z in the output).
 size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup, v3db_layout layout);

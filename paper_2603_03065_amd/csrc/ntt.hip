@@ -25,13 +25,18 @@ __global__ void __launch_bounds__(LDE_THREADS) k_lde_pass3(LdeTask s, Twiddles t
   lde_pass3_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
 }
 
-// log2 of the tile height: T * M <= 8192 words, T <= 16, T <= the other dimension.
-int tile_log(int logM, int other_log) {
+// log2 of the tile height: T * M <= 8192 words, T <= 2^cap, T <= the other dimension.
+int tile_log(int logM, int other_log, int cap) {
   int lt = DFT_LOG_MAX + 1 - logM;
-  if (lt > 4) lt = 4;
+  if (lt > cap) lt = cap;
   if (lt < 0) lt = 0;
   if (lt > other_log) lt = other_log;
   return lt;
+}
+
+__global__ void k_fill_pattern(uint64_t *__restrict__ x, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    x[i] = (i * 0x9E3779B97F4A7C15ull) >> 1;  // below 2^63 < p
 }
 
 }  // namespace
@@ -64,35 +69,45 @@ v3db_status build_twiddles(v3db_ctx *ctx) {
   return hip_check(hipMemcpy(buf, host.data(), host.size() * 8, hipMemcpyHostToDevice), "upload twiddles");
 }
 
+static void free_plan(v3db_ctx *ctx, LdePlan &p);
+
 void free_twiddles(v3db_ctx *ctx) {
   if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, (4 * (size_t(1) << TW_HALF) + 2 * DFT_N) * 8);
   ctx->tw = Twiddles{};
-  for (auto &kv : ctx->plans) {
-    const LdePlan &p = kv.second;
-    const size_t bytes = ((size_t(1) << (p.L2 + p.log_blowup)) + (size_t(1) << p.L1)) * 8;
-    ctx_free(ctx, p.d_twist, bytes);
-  }
+  for (auto &kv : ctx->plans) free_plan(ctx, kv.second);
   ctx->plans.clear();
 }
 
-v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out) {
-  auto key = std::make_tuple(log_rows, log_blowup, shift);
-  auto it = ctx->plans.find(key);
-  if (it != ctx->plans.end()) {
-    *out = &it->second;
-    return V3DB_OK;
-  }
-  LdePlan p{};
+LdeSchedule default_schedule(uint32_t log_rows, uint32_t log_blowup) {
+  LdeSchedule s{};
+  // n2 = 2^L2 with B*n2 <= 2^14 (pass 2 holds B*n2 words per residue in LDS), n1 <= 2^12
+  s.L2 = log_rows / 2;
+  if (s.L2 + log_blowup > 14) s.L2 = 14 - log_blowup;
+  s.cap1 = s.cap2 = s.cap3 = 4;
+  s.chunk = LDE_CHUNK_COLS;
+  s.us = 0;
+  return s;
+}
+
+bool schedule_valid(const LdeSchedule &s, uint32_t log_rows, uint32_t log_blowup) {
+  if (s.L2 > log_rows || s.L2 + log_blowup > 14 || log_rows - s.L2 > (uint32_t)DFT_LOG_MAX) return false;
+  if (s.L2 > (uint32_t)DFT_LOG_MAX) return false;
+  if (s.cap1 > 4 || s.cap2 > 4 || s.cap3 > 4) return false;
+  return s.chunk >= 1 && s.chunk <= LDE_MAX_CHUNK_COLS;
+}
+
+static v3db_status build_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift,
+                              const LdeSchedule &sched, LdePlan &p) {
+  p = LdePlan{};
   p.log_rows = log_rows;
   p.log_blowup = log_blowup;
   p.shift = shift;
-  // n2 = 2^L2 with B*n2 <= 2^14 (pass 2 holds B*n2 words per residue in LDS), n1 <= 2^12
-  p.L2 = log_rows / 2;
-  if (p.L2 + log_blowup > 14) p.L2 = 14 - log_blowup;
+  p.L2 = sched.L2;
   p.L1 = log_rows - p.L2;
-  p.logT1 = tile_log(p.L1, p.L2);
-  p.logT2 = tile_log(p.L2 + log_blowup, p.L1);
-  p.logT3 = tile_log(p.L1, p.L2 + log_blowup);
+  p.logT1 = tile_log(p.L1, p.L2, sched.cap1);
+  p.logT2 = tile_log(p.L2 + log_blowup, p.L1, sched.cap2);
+  p.logT3 = tile_log(p.L1, p.L2 + log_blowup, sched.cap3);
+  p.chunk = sched.chunk;
   const size_t n1 = size_t(1) << p.L1, n2 = size_t(1) << p.L2, B = size_t(1) << log_blowup;
   std::vector<uint64_t> host(B * n2 + n1);
   // twist[r][j] = (s^n1 * w_{B n2}^r)^j
@@ -124,6 +139,38 @@ v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint
   }
   p.d_twist = buf;
   p.d_scale = buf + B * n2;
+  return V3DB_OK;
+}
+
+static void free_plan(v3db_ctx *ctx, LdePlan &p) {
+  const size_t bytes = ((size_t(1) << (p.L2 + p.log_blowup)) + (size_t(1) << p.L1)) * 8;
+  ctx_free(ctx, p.d_twist, bytes);
+  p.d_twist = p.d_scale = nullptr;
+}
+
+void drop_plans(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup) {
+  for (auto it = ctx->plans.begin(); it != ctx->plans.end();) {
+    if (std::get<0>(it->first) == log_rows && std::get<1>(it->first) == log_blowup) {
+      free_plan(ctx, it->second);
+      it = ctx->plans.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out) {
+  auto key = std::make_tuple(log_rows, log_blowup, shift);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = &it->second;
+    return V3DB_OK;
+  }
+  auto tk = ctx->tuned.find({log_rows, log_blowup});
+  const LdeSchedule sched = tk != ctx->tuned.end() ? tk->second : default_schedule(log_rows, log_blowup);
+  LdePlan p;
+  v3db_status st = build_plan(ctx, log_rows, log_blowup, shift, sched, p);
+  if (st != V3DB_OK) return st;
   *out = &(ctx->plans[key] = p);
   return V3DB_OK;
 }
@@ -131,7 +178,7 @@ v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint
 size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup, v3db_layout layout) {
   const size_t y = (size_t(n_cols) << log_rows) * 8;
   if (layout == V3DB_LAYOUT_NATURAL) return y;
-  const uint32_t chunk = n_cols < LDE_CHUNK_COLS ? n_cols : LDE_CHUNK_COLS;
+  const uint32_t chunk = n_cols < LDE_MAX_CHUNK_COLS ? n_cols : LDE_MAX_CHUNK_COLS;
   return y + size_t(chunk) * (size_t(8) << (log_rows + log_blowup));
 }
 
@@ -185,13 +232,108 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
   hipLaunchKernelGGL(k_lde_pass1, dim3(t1, n_cols), dim3(LDE_THREADS), sh1, stream, s, tw);
   // a chunk of columns at a time through passes 2 and 3, so a chunk's Z is still
   // in the Infinity Cache when pass 3 reads it
-  const uint32_t chunk = n_cols < LDE_CHUNK_COLS ? n_cols : LDE_CHUNK_COLS;
+  const uint32_t chunk = n_cols < plan->chunk ? n_cols : plan->chunk;
   for (uint32_t c0 = 0; c0 < n_cols; c0 += chunk) {
     const uint32_t nc = (n_cols - c0) < chunk ? (n_cols - c0) : chunk;
     hipLaunchKernelGGL(k_lde_pass2, dim3(t2, nc), dim3(LDE_THREADS), sh2, stream, s, tw, (int)c0);
     hipLaunchKernelGGL(k_lde_pass3, dim3(t3, nc), dim3(LDE_THREADS), sh3, stream, s, tw, (int)c0);
   }
   return hip_check(hipGetLastError(), "LDE launch");
+}
+
+// Time one schedule on the given buffers: the best of three runs after a warm-up.
+static v3db_status time_schedule(v3db_ctx *ctx, const LdeSchedule &sc, uint32_t L, uint32_t b, uint32_t n_cols,
+                                 v3db_layout layout, uint64_t *trace, uint64_t *lde, uint64_t *scratch,
+                                 hipStream_t stream, hipEvent_t e0, hipEvent_t e1, double *us) {
+  // a private plan with this schedule (shift 7; the shift does not change the work)
+  LdePlan p;
+  v3db_status st = build_plan(ctx, L, b, 7, sc, p);
+  if (st != V3DB_OK) return st;
+  auto key = std::make_tuple(L, b, uint64_t(7));
+  auto old = ctx->plans.find(key);
+  LdePlan saved{};
+  const bool had = old != ctx->plans.end();
+  if (had) saved = old->second;
+  ctx->plans[key] = p;
+  double best = 1e30;
+  for (int rep = 0; rep < 4 && st == V3DB_OK; rep++) {
+    hipError_t e = hipEventRecord(e0, stream);
+    if (e == hipSuccess) st = enqueue_lde(ctx, trace, n_cols, L, b, 7, layout, lde, scratch, stream);
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_check(e, "autotune timing");
+    if (rep > 0 && st == V3DB_OK) best = std::min(best, double(ms) * 1e3);
+  }
+  if (had) ctx->plans[key] = saved;
+  else ctx->plans.erase(key);
+  free_plan(ctx, p);
+  *us = best;
+  return st;
+}
+
+v3db_status autotune_lde(v3db_ctx *ctx, uint32_t L, uint32_t b, uint32_t n_cols, v3db_layout layout,
+                         LdeSchedule *out) {
+  const size_t n = size_t(1) << L, N = n << b;
+  uint64_t *trace = nullptr, *lde = nullptr, *scratch = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  v3db_status st = ctx_alloc(ctx, (void **)&trace, n_cols * n * 8, "autotune trace");
+  if (st == V3DB_OK) st = ctx_alloc(ctx, (void **)&lde, n_cols * N * 8, "autotune LDE");
+  const size_t sb = lde_scratch_bytes(n_cols, L, b, layout);
+  if (st == V3DB_OK) st = ctx_alloc(ctx, (void **)&scratch, sb, "autotune scratch");
+  hipError_t e = hipSuccess;
+  if (st == V3DB_OK) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+  if (st == V3DB_OK && e == hipSuccess) e = hipEventCreate(&e0);
+  if (st == V3DB_OK && e == hipSuccess) e = hipEventCreate(&e1);
+  if (st == V3DB_OK && e != hipSuccess) st = hip_check(e, "autotune setup");
+  if (st == V3DB_OK) {
+    hipLaunchKernelGGL(k_fill_pattern, dim3(1024), dim3(256), 0, stream, trace, n_cols * n);
+    st = hip_check(hipGetLastError(), "autotune fill");
+  }
+  LdeSchedule best = default_schedule(L, b);
+  double best_us = 0;
+  if (st == V3DB_OK) st = time_schedule(ctx, best, L, b, n_cols, layout, trace, lde, scratch, stream, e0, e1, &best_us);
+  auto consider = [&](LdeSchedule c) {
+    if (st != V3DB_OK || !schedule_valid(c, L, b)) return;
+    double us = 0;
+    st = time_schedule(ctx, c, L, b, n_cols, layout, trace, lde, scratch, stream, e0, e1, &us);
+    if (st == V3DB_OK && us < best_us * 0.98) {
+      best = c;
+      best_us = us;
+    }
+  };
+  // coordinate search: the split, then each pass's tile cap, then the column chunk
+  const LdeSchedule d = best;
+  for (int delta : {-2, -1, 1, 2}) {
+    LdeSchedule c = d;
+    if ((int)c.L2 + delta < 0) continue;
+    c.L2 = (uint32_t)((int)c.L2 + delta);
+    consider(c);
+  }
+  for (int pass = 1; pass <= 3; pass++)
+    for (uint32_t cap : {2u, 3u}) {
+      LdeSchedule c = best;
+      (pass == 1 ? c.cap1 : pass == 2 ? c.cap2 : c.cap3) = cap;
+      consider(c);
+    }
+  if (n_cols > 1)
+    for (uint32_t ch : {4u, 16u}) {
+      LdeSchedule c = best;
+      c.chunk = ch;
+      consider(c);
+    }
+  if (stream) (void)hipStreamDestroy(stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  ctx_free(ctx, scratch, sb);
+  ctx_free(ctx, lde, n_cols * N * 8);
+  ctx_free(ctx, trace, n_cols * n * 8);
+  if (st != V3DB_OK) return st;
+  best.us = best_us;
+  *out = best;
+  return V3DB_OK;
 }
 
 }  // namespace v3db

@@ -82,3 +82,14 @@ def test_null_context_is_rejected_without_device(v3db):
     assert b"NULL ctx" in lib.v3db_last_error()
     assert lib.v3db_commit_batch(None, None, 0, None) == 1
     assert lib.v3db_poseidon_permute(None, None, 0, None) == 1
+
+
+def test_schedule_calls_reject_null_arguments_without_device(v3db):
+    lib = v3db.lib()
+    s = v3db._Schedule(12, 3, 6, (ctypes.c_uint32 * 3)(4, 4, 4), 8, 0.0)
+    assert lib.v3db_autotune_lde(None, 12, 3, 8, 0, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
+    assert lib.v3db_get_schedule(None, 12, 3, ctypes.byref(s)) == 1
+    assert lib.v3db_set_schedule(None, ctypes.byref(s)) == 1
+    assert lib.v3db_schedules_save(None, b"/dev/null", None) == 1
+    assert lib.v3db_schedules_load(None, b"/dev/null", None) == 1
