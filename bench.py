@@ -88,7 +88,7 @@ def parse():
                     help="keep the default LDE schedules instead of tuning them before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (reference for the HBM byte counters)")
-    ap.add_argument("--cpu-sample-log-rows", type=int, default=13,
+    ap.add_argument("--cpu-sample-log-rows", type=int, default=17,
                     help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
     return ap.parse_args()
 

@@ -31,15 +31,38 @@ GL_HD void mul_wide(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
   lo = (v << 32) | (uint32_t)t;
 }
 
+#ifdef __HIP_DEVICE_COMPILE__
+// c + a * (2^32 - 1) modulo 2^64 as one v_mad_u64_u32 (written out because the
+// compiler splits a multiply-add whose sum is also compared into two instructions).
+__device__ __forceinline__ uint64_t mad_eps(uint32_t a, uint64_t c) {
+  uint64_t d;
+  asm("v_mad_u64_u32 %0, vcc, %1, -1, %2" : "=&v"(d) : "v"(a), "v"(c) : "vcc");
+  return d;
+}
+#endif
+
 // Reduce hi*2^64 + lo (any 128-bit value) to a relaxed value in [0, 2^64).
 GL_HD uint64_t reduce128(uint64_t lo, uint64_t hi) {
   const uint32_t hh = (uint32_t)(hi >> 32), hl = (uint32_t)hi;
+#ifdef __HIP_DEVICE_COMPILE__
+  // r = lo - hh + b*2^64, s = r + hl*(2^32-1) - c*2^64, so x = s + (c - b)*(2^32-1).
+  // If c and not b, s < 2^64 - 2^33 + 2 has room for 2^32-1; if b and not c,
+  // s >= r >= 2^64 - 2^32 + 1, so subtracting 2^32-1 stays non-negative.
+  unsigned b1, b;
+  const uint32_t r0 = __builtin_subc((uint32_t)lo, hh, 0u, &b1);
+  const uint32_t r1 = __builtin_subc((uint32_t)(lo >> 32), 0u, b1, &b);
+  const uint64_t r = ((uint64_t)r1 << 32) | r0;
+  const uint64_t s = mad_eps(hl, r);
+  const bool c = s < r;
+  return s + (c ? EPS : 0) - (b ? EPS : 0);
+#else
   uint64_t t0;
   if (__builtin_sub_overflow(lo, (uint64_t)hh, &t0)) t0 -= EPS;  // borrowed 2^64 = EPS; t0 >= 2^64 - 2^32 here
   const uint64_t t1 = (uint64_t)hl * EPS;                         // hl * (2^32 - 1)
   uint64_t t2;
   if (__builtin_add_overflow(t0, t1, &t2)) t2 += EPS;            // carried 2^64; cannot carry again
   return t2;
+#endif
 }
 
 GL_HD uint64_t canon(uint64_t x) { return x >= P ? x - P : x; }
@@ -55,9 +78,10 @@ GL_HD uint64_t mul_r(uint64_t a, uint64_t b) {
 GL_HD uint64_t mul(uint64_t a, uint64_t b) { return canon(mul_r(a, b)); }
 
 GL_HD uint64_t add(uint64_t a, uint64_t b) {  // a, b canonical
-  uint64_t s = a + b;
-  if (s < a) return s + EPS;         // a + b - 2^64 + EPS < p
-  return canon(s);
+  // a + b < 2p: subtract p (add 2^64 - p = EPS modulo 2^64) when the sum carried
+  // out of 64 bits or is at least p; written without branches
+  const uint64_t s = a + b, t = s + EPS;
+  return (s < a) | (s >= P) ? t : s;
 }
 
 GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical

@@ -32,7 +32,8 @@ __device__ __forceinline__ uint64_t sbox(uint64_t x) {
 // lo + hi * 2^32 for lo, hi < 2^46, to a relaxed value: with hi = hh*2^32 + hl,
 // the sum is lo + hh*2^64 + hl*2^32 = (hh*(2^32-1) + lo) + hl*2^32 (mod p); the
 // first part is one multiply-add below 2^47, the second adds hl to its high word
-// and a carry out of bit 64 is worth 2^32 - 1 again.
+// and a carry out of bit 64 is worth 2^32 - 1 again (the sum is then below
+// 2^47, far from overflowing once more).
 __device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
   const uint64_t t = (uint64_t)(uint32_t)(hi >> 32) * gl::EPS + lo;
   const uint32_t th = (uint32_t)(t >> 32);
