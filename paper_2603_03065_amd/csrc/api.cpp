@@ -179,11 +179,16 @@ v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budge
   }
   // the round constants followed by one row of zeros (the kernels add "next round's
   // constants" inside every round's linear layer, the last one included)
-  uint64_t table[(ROUNDS + 1) * WIDTH] = {};
+  uint64_t table[POS_TABLE_WORDS] = {};
   memcpy(table, ctx->pos.rc, sizeof(ctx->pos.rc));
+  // then the rows of M[i][j] = a[(j - i) mod 12], for kernels that give each lane one row
+  uint32_t *rows = reinterpret_cast<uint32_t *>(table + (ROUNDS + 1) * WIDTH);
+  for (int i = 0; i < WIDTH; i++)
+    for (int j = 0; j < WIDTH; j++) rows[i * WIDTH + j] = (uint32_t)ctx->pos.circ[(j - i + WIDTH) % WIDTH];
   v3db_status st = ctx_alloc(ctx, (void **)&ctx->d_pos, sizeof(table), "Poseidon constants");
   if (st == V3DB_OK)
     st = hip_check(hipMemcpy(ctx->d_pos, table, sizeof(table), hipMemcpyHostToDevice), "upload Poseidon constants");
+  if (st == V3DB_OK) ctx->d_circ_rows = reinterpret_cast<const uint32_t *>(ctx->d_pos + (ROUNDS + 1) * WIDTH);
   if (st == V3DB_OK) st = build_twiddles(ctx);
   if (st != V3DB_OK) {
     v3db_ctx_destroy(ctx);
@@ -204,7 +209,7 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   for (auto &kv : ctx->scratch) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
   ctx->scratch.clear();
   free_twiddles(ctx);
-  ctx_free(ctx, ctx->d_pos, (ROUNDS + 1) * WIDTH * 8);
+  ctx_free(ctx, ctx->d_pos, POS_TABLE_WORDS * 8);
   delete ctx;
 }
 

@@ -113,6 +113,32 @@ __global__ void __launch_bounds__(POS_THREADS) k_batch_merkle(const BJob *__rest
   }
 }
 
+// The same for depths with few nodes in all: 16 lanes per node (wide_permute).
+__global__ void __launch_bounds__(pos::WIDE_THREADS) k_batch_merkle_wide(const BJob *__restrict__ jobs,
+                                                                         const BRange *__restrict__ ranges,
+                                                                         int n_ranges, int depth,
+                                                                         const uint64_t *__restrict__ rc,
+                                                                         const uint32_t *__restrict__ circ_rows) {
+  __shared__ uint64_t xs[2 * pos::WIDE_THREADS];
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint32_t level = j.logN - depth;
+  const uint64_t count = uint64_t(1) << level;
+  const int g = threadIdx.x % pos::WIDE_GROUP, grp = threadIdx.x / pos::WIDE_GROUP;
+  const uint64_t k = uint64_t(blockIdx.x - r.first) * pos::WIDE_PER_BLOCK + grp;
+  const bool live = k < count;
+  const uint64_t off_below = (uint64_t(2) << j.logN) - (uint64_t(2) << (level + 1));
+  const uint64_t off_here = (uint64_t(2) << j.logN) - (uint64_t(2) << level);
+  uint64_t s = 0;
+  if (live && g < 2 * DIGEST) s = j.tree[(off_below + 2 * k) * DIGEST + g];
+  s = pos::wide_permute(s, g, grp, xs, rc, circ_rows);
+  if (live && g < DIGEST) {
+    const uint64_t v = gl::canon(s);
+    j.tree[(off_here + k) * DIGEST + g] = v;
+    if (level == j.cap_height) j.cap[k * DIGEST + g] = v;
+  }
+}
+
 size_t tree_digests(uint32_t log_leaves, uint32_t cap_height) {
   return (size_t(2) << log_leaves) - (size_t(1) << cap_height);
 }
@@ -180,7 +206,7 @@ v3db_status commit_single(v3db_ctx *ctx, const v3db_commit_job &j, void *scratch
 }
 
 struct Phase {
-  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth
+  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth, 6 Merkle depth with 16 lanes per node
   int depth;  // Merkle depth
   size_t ranges_off, n_ranges;
   uint32_t blocks;
@@ -229,12 +255,18 @@ void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3d
   for (size_t i = 0; i < nj; i++)
     max_depth = std::max(max_depth, jobs[i].log_rows + jobs[i].log_blowup - jobs[i].cap_height);
   for (uint32_t d = 1; d <= max_depth; d++) {
-    add_phase(5, (int)d, 0, [&](size_t i) -> uint32_t {
+    auto nodes_of = [&](size_t i) -> uint64_t {
       const uint32_t logN = jobs[i].log_rows + jobs[i].log_blowup;
       if (logN < d || logN - d < jobs[i].cap_height) return 0;
-      const uint64_t nodes = uint64_t(1) << (logN - d);
-      return (uint32_t)((nodes + MERKLE_NODES - 1) / MERKLE_NODES);
-    });
+      return uint64_t(1) << (logN - d);
+    };
+    uint64_t total = 0;
+    for (size_t i = 0; i < nj; i++) total += nodes_of(i);
+    // few nodes at this depth in all: 16 lanes per node for a shorter chain
+    const bool wide = total <= MERKLE_WIDE_MAX_NODES;
+    const uint64_t per_block = wide ? pos::WIDE_PER_BLOCK : MERKLE_NODES;
+    add_phase(wide ? 6 : 5, (int)d, 0,
+              [&](size_t i) -> uint32_t { return (uint32_t)((nodes_of(i) + per_block - 1) / per_block); });
   }
 }
 
@@ -311,9 +343,12 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
                          tw);
     else if (ph.kind == 4)
       hipLaunchKernelGGL(k_batch_leaf, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ctx->d_pos, c);
-    else
+    else if (ph.kind == 5)
       hipLaunchKernelGGL(k_batch_merkle, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ph.depth,
                          ctx->d_pos, c);
+    else
+      hipLaunchKernelGGL(k_batch_merkle_wide, dim3(ph.blocks), dim3(pos::WIDE_THREADS), 0, cs, d_jobs, rr, nr,
+                         ph.depth, ctx->d_pos, ctx->d_circ_rows);
   }
   const hipError_t le = hipGetLastError();
   hipGraph_t graph = nullptr;

@@ -67,6 +67,12 @@ GL_HD uint64_t reduce128(uint64_t lo, uint64_t hi) {
 
 GL_HD uint64_t canon(uint64_t x) { return x >= P ? x - P : x; }
 
+// x * 2^K (0 < K < 64), relaxed: the 128-bit product is a pair of shifts.
+template <int K>
+GL_HD uint64_t mul_pow2(uint64_t x) {
+  return reduce128(x << K, x >> (64 - K));
+}
+
 // relaxed * relaxed -> relaxed
 GL_HD uint64_t mul_r(uint64_t a, uint64_t b) {
   uint64_t lo, hi;
@@ -85,9 +91,13 @@ GL_HD uint64_t add(uint64_t a, uint64_t b) {  // a, b canonical
 }
 
 GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical
-  uint64_t d = a - b;
-  if (a < b) d -= EPS;               // a - b + p = d - 2^64 + p = d - EPS
-  return d;
+  // a - b + p = d - 2^64 + p = d - EPS when the subtraction borrowed; the borrow
+  // is taken from the carry chain rather than from a second comparison
+  unsigned b1, bw;
+  const uint32_t d0 = __builtin_subc((uint32_t)a, (uint32_t)b, 0u, &b1);
+  const uint32_t d1 = __builtin_subc((uint32_t)(a >> 32), (uint32_t)(b >> 32), b1, &bw);
+  const uint64_t d = ((uint64_t)d1 << 32) | d0;
+  return d - (bw ? EPS : 0);
 }
 
 // relaxed a + canonical b -> relaxed

@@ -15,6 +15,11 @@
 namespace v3db {
 
 constexpr int WIDTH = 12, RATE = 8, DIGEST = 4, ROUNDS = 30, FULL_HALF = 4;
+// Device Poseidon table: (ROUNDS + 1) x WIDTH round-constant words, then WIDTH x WIDTH
+// 32-bit matrix entries (half as many 64-bit words).
+// Tree levels of at most this many nodes use 16 lanes per node (shorter latency).
+constexpr uint64_t MERKLE_WIDE_MAX_NODES = uint64_t(1) << 15;
+constexpr size_t POS_TABLE_WORDS = (ROUNDS + 1) * WIDTH + WIDTH * WIDTH / 2;
 constexpr int TW_LOG = 26;        // largest transform, 2^26 points
 constexpr int TW_HALF = 13;       // two-level twiddle table: 2^13 x 2^13
 constexpr int DFT_LOG_MAX = 12;   // largest in-LDS sub-transform, 4096 points
@@ -29,7 +34,7 @@ struct PoseidonTables {
 struct Twiddles {
   uint64_t *fwd_lo, *fwd_hi;   // w^i and w^(2^13 i), w = w_{2^26}, i < 2^13
   uint64_t *inv_lo, *inv_hi;   // same for w^-1
-  uint64_t *dft_fwd, *dft_inv; // w_4096^t and w_4096^-t, t < 4096
+  uint64_t *bfly_fwd, *bfly_inv; // radix-8 butterfly twiddle rows, forward and inverse (lde_dev.h)
 };
 
 // Schedule of the LDE passes for one (log_rows, log_blowup): the split
@@ -48,7 +53,12 @@ struct LdePlan {
   uint64_t shift;
   uint64_t *d_twist;  // [B][n2]: (shift^n1 * w_{B n2}^r)^j
   uint64_t *d_scale;  // [n1]: n^-1 * shift^k1
+  uint64_t *d_ztw;    // [n1][B n2]: w_N^(k1 e) for N <= 2^ZTW_MAX_LOG, else null
 };
+
+// Largest extension (log2 rows) whose pass-2 twiddles w_N^(k1 e) are kept as a
+// full table (8 N bytes per shape) instead of two lookups and a product.
+constexpr uint32_t ZTW_MAX_LOG = 22;
 
 struct ScratchBuf {
   void *ptr = nullptr;
@@ -66,7 +76,9 @@ struct v3db_ctx {
   size_t allocated = 0;    // bytes currently held by this context
   uint32_t mds_attempts = 0;
   v3db::PoseidonTables pos{};
-  uint64_t *d_pos = nullptr;  // device copy of pos.rc (flat 360) followed by circ as u64 (12)
+  uint64_t *d_pos = nullptr;         // POS_TABLE_WORDS: round constants (ROUNDS + 1 rows, last zero),
+                                    // then the matrix rows M[i][j] as 32-bit words
+  const uint32_t *d_circ_rows = nullptr;  // inside d_pos
   v3db::Twiddles tw{};
   std::map<std::tuple<uint32_t, uint32_t, uint64_t>, v3db::LdePlan> plans;
   std::map<std::pair<uint32_t, uint32_t>, v3db::LdeSchedule> tuned;  // autotuned schedules

@@ -32,7 +32,6 @@ namespace v3db {
 namespace lde {
 
 constexpr int LDE_THREADS = 512;
-constexpr int DFT_N = 1 << DFT_LOG_MAX;  // 4096
 constexpr int TILE_ELEMS = 8192;         // T * M per tile
 constexpr int MAX_PER_THREAD = TILE_ELEMS / LDE_THREADS;
 
@@ -40,23 +39,43 @@ __device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
   return bits ? (__brev(x) >> (32 - bits)) : 0u;
 }
 
+// Position of word w of a tile row in LDS. Rows are 2^k words; the XOR of two
+// right shifts is an invertible linear map on k-bit indices, chosen so that the
+// access patterns of the passes (runs of consecutive words, the strided words
+// of each radix-8 butterfly, and bit-reversed reads) spread a half-wave over
+// distinct banks (at most 2 lanes per 8-byte bank slot). Linear over XOR:
+// swz(a ^ b) = swz(a) ^ swz(b).
+__device__ __forceinline__ int swz(int w) { return w ^ (w >> 3) ^ (w >> 8); }
+
 // w^e for e < 2^26 from the two-level table (w = w_{2^26} or its inverse).
 __device__ __forceinline__ uint64_t tw_pow(const uint64_t *__restrict__ lo, const uint64_t *__restrict__ hi,
                                            uint32_t e) {
   return gl::mul(hi[e >> TW_HALF], lo[e & ((1u << TW_HALF) - 1)]);
 }
 
-// Powers of w_8 = 7^((p-1)/8) (forward) and of its inverse; all are +-2^(24 k),
-// so with these compile-time operands the products need only half the partial
-// products.
-__device__ __forceinline__ uint64_t w8(int k, bool inv) {
-  constexpr uint64_t F[4] = {1ull, 18446744069397807105ull, 281474976710656ull, 18446742969902956801ull};
-  constexpr uint64_t I[4] = {1ull, 1099511627520ull, 18446462594437873665ull, 16777216ull};
-  return inv ? I[k] : F[k];
+// The internal twiddles of a radix-8 butterfly are powers of w_8 = 7^((p-1)/8)
+// = -2^24 (so w_8^2 = 2^48, w_8^3 = -2^72; inverse: 2^72, -2^48, 2^24). The
+// product (u - w) * w_8^k is formed with the sign folded into the subtraction
+// ((w - u) * 2^m for -2^m) and the power of two as shifts where that is cheaper
+// than a multiplication (2^24, 2^48); 2^72 = 2^40 - 2^8 (mod p) takes the
+// general product.
+constexpr uint64_t TWO_72 = 1099511627520ull;
+
+template <int K, bool INV>
+__device__ __forceinline__ uint64_t sub_w8(uint64_t u, uint64_t w) {
+  if (K == 0) return gl::sub(u, w);
+  if (!INV) {
+    if (K == 1) return gl::canon(gl::mul_pow2<24>(gl::sub(w, u)));
+    if (K == 2) return gl::canon(gl::mul_pow2<48>(gl::sub(u, w)));
+    return gl::mul(gl::sub(w, u), TWO_72);
+  }
+  if (K == 1) return gl::mul(gl::sub(u, w), TWO_72);
+  if (K == 2) return gl::canon(gl::mul_pow2<48>(gl::sub(w, u)));
+  return gl::canon(gl::mul_pow2<24>(gl::sub(u, w)));
 }
 
-// Size-R transform in registers (R = 2, 4, 8) by radix-2 stages.
-// dif: natural order in, bit-reversed order out. dit: bit-reversed in, natural out.
+// Size-R transform in registers (R = 2, 4, 8) by radix-2 decimation-in-frequency
+// stages: natural order in, bit-reversed order out.
 template <int R, bool INV>
 __device__ __forceinline__ void reg_dif(uint64_t v[R]) {
 #pragma unroll
@@ -67,24 +86,12 @@ __device__ __forceinline__ void reg_dif(uint64_t v[R]) {
       for (int i = 0; i < h; i++) {
         const uint64_t u = v[b + i], w = v[b + i + h];
         v[b + i] = gl::add(u, w);
-        const uint64_t d = gl::sub(u, w);
-        v[b + i + h] = i ? gl::mul(d, w8(i * (8 / (2 * h)), INV)) : d;
-      }
-}
-
-template <int R, bool INV>
-__device__ __forceinline__ void reg_dit(uint64_t v[R]) {
-#pragma unroll
-  for (int h = 1; h < R; h <<= 1)
-#pragma unroll
-    for (int b = 0; b < R; b += 2 * h)
-#pragma unroll
-      for (int i = 0; i < h; i++) {
-        const uint64_t u = v[b + i];
-        uint64_t w = v[b + i + h];
-        if (i) w = gl::mul(w, w8(i * (8 / (2 * h)), INV));
-        v[b + i] = gl::add(u, w);
-        v[b + i + h] = gl::sub(u, w);
+        switch (i * (8 / (2 * h))) {
+          case 0: v[b + i + h] = sub_w8<0, INV>(u, w); break;
+          case 1: v[b + i + h] = sub_w8<1, INV>(u, w); break;
+          case 2: v[b + i + h] = sub_w8<2, INV>(u, w); break;
+          default: v[b + i + h] = sub_w8<3, INV>(u, w); break;
+        }
       }
 }
 
@@ -93,59 +100,52 @@ __device__ __forceinline__ int brev_r(int j) {
   return R == 8 ? ((j & 1) << 2 | (j & 2) | (j >> 2)) : R == 4 ? ((j & 1) << 1 | (j >> 1)) : j;
 }
 
+// Butterfly twiddle rows of the radix-8 passes: for sub-block size S = 2^logS
+// (3 <= logS <= 12), row i < S/8 holds w_S^(i * bitrev3(j)), j = 0..7, so a
+// butterfly reads its seven twiddles as one 64-byte row. Rows of all sizes are
+// concatenated, smallest S first.
+__host__ __device__ constexpr int bfly_row0(int logS) { return (1 << (logS - 3)) - 1; }
+constexpr int BFLY_ROWS = (1 << (DFT_LOG_MAX - 2)) - 1;  // rows for logS = 3..12
+
 // One radix-R pass of a decimation-in-frequency transform over T rows of
 // 2^logM words in LDS (row stride rs): sub-blocks of 2^logS words, each
 // butterfly takes the R words i + j*2^logS/R, transforms them, and multiplies
-// output slot j (frequency bitrev(j)) by w_S^(i * bitrev(j)). tw = w_4096^t.
+// output slot j (frequency bitrev(j)) by w_S^(i * bitrev(j)) (radix 8 with
+// logS > 3 only: for the other passes i is always 0).
 template <int R, bool INV>
 __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, int logS,
-                                         const uint64_t *__restrict__ tw) {
+                                         const uint64_t *__restrict__ bfly) {
   constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
   const int logStride = logS - LR;
   const int per_row = 1 << (logM - LR);
   const int nb = T * per_row;
+  const bool twiddled = R == 8 && logS > 3;
+  const uint64_t *rows = bfly + 8 * bfly_row0(R == 8 ? (logS > 3 ? logS : 3) : 3);
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int t = b >> (logM - LR);
     const int q = b & (per_row - 1);
     const int i = q & ((1 << logStride) - 1);
-    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
+    // word (q >> logStride) << logS | i | j << logStride of row t; the three parts
+    // have disjoint bits, so its swizzled position is the XOR of theirs
+    uint64_t *row = sh + t * rs;
+    const int wb = swz(((q >> logStride) << logS) + i);
     uint64_t v[R];
 #pragma unroll
-    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
+    for (int j = 0; j < R; j++) v[j] = row[wb ^ swz(j << logStride)];
     reg_dif<R, INV>(v);
-    if (i) {
+    if (twiddled) {
+      const ulonglong2 *trow = reinterpret_cast<const ulonglong2 *>(rows + 8 * i);
+      uint64_t tw[8];
 #pragma unroll
-      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
+      for (int k = 0; k < 4; k++) {
+        const ulonglong2 x = trow[k];
+        tw[2 * k] = x.x, tw[2 * k + 1] = x.y;
+      }
+#pragma unroll
+      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[j]);
     }
 #pragma unroll
-    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
-  }
-}
-
-// One radix-R pass of a decimation-in-time transform: combines R transformed
-// sub-blocks of 2^logS/R words into one of 2^logS words.
-template <int R, bool INV>
-__device__ __forceinline__ void dit_pass(uint64_t *sh, int T, int logM, int rs, int logS,
-                                         const uint64_t *__restrict__ tw) {
-  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
-  const int logStride = logS - LR;
-  const int per_row = 1 << (logM - LR);
-  const int nb = T * per_row;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    const int t = b >> (logM - LR);
-    const int q = b & (per_row - 1);
-    const int i = q & ((1 << logStride) - 1);
-    uint64_t *base = sh + t * rs + ((q >> logStride) << logS) + i;
-    uint64_t v[R];
-#pragma unroll
-    for (int j = 0; j < R; j++) v[j] = base[j << logStride];
-    if (i) {
-#pragma unroll
-      for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[(i * brev_r<R>(j)) << (DFT_LOG_MAX - logS)]);
-    }
-    reg_dit<R, INV>(v);
-#pragma unroll
-    for (int j = 0; j < R; j++) base[j << logStride] = v[j];
+    for (int j = 0; j < R; j++) row[wb ^ swz(j << logStride)] = v[j];
   }
 }
 
@@ -154,42 +154,25 @@ __device__ __forceinline__ void dit_pass(uint64_t *sh, int T, int logM, int rs, 
 // Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
 // were done another way).
 template <bool INV>
-__device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ tw) {
+__device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ bfly) {
   int logS = logS0;
   for (; logS >= 3; logS -= 3) {
-    dif_pass<8, INV>(sh, T, logM, rs, logS, tw);
+    dif_pass<8, INV>(sh, T, logM, rs, logS, bfly);
     __syncthreads();
   }
   if (logS == 2) {
-    dif_pass<4, INV>(sh, T, logM, rs, 2, tw);
+    dif_pass<4, INV>(sh, T, logM, rs, 2, bfly);
     __syncthreads();
   } else if (logS == 1) {
-    dif_pass<2, INV>(sh, T, logM, rs, 1, tw);
+    dif_pass<2, INV>(sh, T, logM, rs, 1, bfly);
     __syncthreads();
   }
 }
 
 template <bool INV>
-__device__ __forceinline__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
-  dif_rows_from<INV>(sh, T, logM, logM, rs, tw);
+__device__ __forceinline__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ bfly) {
+  dif_rows_from<INV>(sh, T, logM, logM, rs, bfly);
 }
-
-template <bool INV>
-__device__ void dit_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ tw) {
-  int logS = logM % 3;
-  if (logS == 2) {
-    dit_pass<4, INV>(sh, T, logM, rs, 2, tw);
-    __syncthreads();
-  } else if (logS == 1) {
-    dit_pass<2, INV>(sh, T, logM, rs, 1, tw);
-    __syncthreads();
-  }
-  for (logS += 3; logS <= logM; logS += 3) {
-    dit_pass<8, INV>(sh, T, logM, rs, logS, tw);
-    __syncthreads();
-  }
-}
-
 
 // One trace's LDE as the passes see it. Column c of the trace is trace + c*n,
 // of Y (pass 1 output) y + c*n, of the output lde + c*N, and the Z rows of
@@ -203,6 +186,7 @@ struct LdeTask {
   uint64_t *lde;
   const uint64_t *twist;  // [B][n2]: (shift^n1 w_{B n2}^r)^i
   const uint64_t *scale;  // [n1]: n^-1 shift^k1
+  const uint64_t *ztw;    // [n1][W]: w_N^(k1 e), or null (then from the two-level table)
   uint64_t zstride;
   int L, b, L1, L2;       // log n, log blowup, log n1, log n2 (n = n1 n2)
   int logT1, logT2, logT3;
@@ -223,15 +207,15 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
   const int total = T * n1;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = e & (T - 1), j1 = e >> s.logT1;
-    sh[t * rs + j1] = a[size_t(j1) * n2 + j2_0 + t];
+    sh[t * rs + swz(j1)] = a[size_t(j1) * n2 + j2_0 + t];
   }
   __syncthreads();
-  dif_rows<true>(sh, T, s.L1, rs, tw.dft_inv);
+  dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv);
   const int shl = TW_LOG - s.L;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = e & (T - 1), k1 = e >> s.logT1;
     const uint32_t j2 = j2_0 + t;
-    uint64_t v = sh[t * rs + brev(k1, s.L1)];
+    uint64_t v = sh[t * rs + swz(brev(k1, s.L1))];
     const uint32_t ex = (uint32_t)((uint64_t(j2) * k1) & (n - 1));
     if (ex) v = gl::mul(v, tw_pow(tw.inv_lo, tw.inv_hi, ex << shl));
     y[size_t(k1) * n2 + j2] = v;
@@ -257,17 +241,17 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
   const int total_in = T << s.L2;
   for (int e = threadIdx.x; e < total_in; e += blockDim.x) {
     const int t = e >> s.L2, j = e & (n2 - 1);
-    sh[t * rs + j] = y[size_t(k1_0 + t) * n2 + j];
+    sh[t * rs + swz(j)] = y[size_t(k1_0 + t) * n2 + j];
   }
   __syncthreads();
-  dif_rows<true>(sh, T, s.L2, rs, tw.dft_inv);
+  dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
   uint64_t c[MAX_PER_THREAD];
 #pragma unroll
   for (int m = 0; m < MAX_PER_THREAD; m++) {
     const int e = threadIdx.x + m * LDE_THREADS;
     if (e < total_in) {
       const int t = e >> s.L2, i = e & (n2 - 1);
-      c[m] = gl::mul(sh[t * rs + brev(i, s.L2)], s.scale[k1_0 + t]);
+      c[m] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
     }
   }
   __syncthreads();
@@ -276,20 +260,26 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
     const int e = threadIdx.x + m * LDE_THREADS;
     if (e < total_in) {
       const int t = e >> s.L2, i = e & (n2 - 1);
-      for (int j = 0; j < B; j++) sh[t * rs + i + (j << s.L2)] = gl::mul(c[m], s.twist[(brev(j, s.b) << s.L2) + i]);
+      const int wi = swz(i);
+      for (int j = 0; j < B; j++) sh[t * rs + (wi ^ swz(j << s.L2))] = gl::mul(c[m], s.twist[(brev(j, s.b) << s.L2) + i]);
     }
   }
   __syncthreads();
-  dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.dft_fwd);
+  dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd);
   const int total_out = T << LW;
   const int shl = TW_LOG - logN;
   for (int e = threadIdx.x; e < total_out; e += blockDim.x) {
     const int t = e >> LW, f = e & (W - 1);
     const uint32_t k1 = k1_0 + t;
-    uint64_t v = sh[t * rs + brev(f, LW)];
-    const uint32_t ex = (uint32_t)((uint64_t(k1) * f) & (N - 1));
-    if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
-    zc[(size_t(k1) << LW) + f] = v;
+    uint64_t v = sh[t * rs + swz(brev(f, LW))];
+    const size_t zi = (size_t(k1) << LW) + f;
+    if (s.ztw) {
+      v = gl::mul(v, s.ztw[zi]);
+    } else {
+      const uint32_t ex = (uint32_t)((uint64_t(k1) * f) & (N - 1));
+      if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
+    }
+    zc[zi] = v;
   }
 }
 
@@ -307,19 +297,19 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
   const int total = T * n1;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = e & (T - 1), k1 = e >> s.logT3;
-    sh[t * rs + k1] = zc[(size_t(k1) << LW) + e0 + t];
+    sh[t * rs + swz(k1)] = zc[(size_t(k1) << LW) + e0 + t];
   }
   __syncthreads();
-  dif_rows<false>(sh, T, s.L1, rs, tw.dft_fwd);
+  dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd);
   if (!s.bitrev) {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e & (T - 1), m2 = e >> s.logT3;
-      out[size_t(e0 + t) + size_t(W) * m2] = sh[t * rs + brev(m2, s.L1)];
+      out[size_t(e0 + t) + size_t(W) * m2] = sh[t * rs + swz(brev(m2, s.L1))];
     }
   } else {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e >> s.L1, p = e & (n1 - 1);
-      out[size_t(brev(e0 + t, LW)) * n1 + p] = sh[t * rs + p];
+      out[size_t(brev(e0 + t, LW)) * n1 + p] = sh[t * rs + swz(p)];
     }
   }
 }

@@ -34,6 +34,16 @@ int tile_log(int logM, int other_log, int cap) {
   return lt;
 }
 
+// ztw[k1 * W + e] = w_N^(k1 e mod N), from the two-level table of w_{2^26}.
+__global__ void k_fill_ztw(uint64_t *__restrict__ ztw, int LW, int logN, Twiddles tw) {
+  const size_t N = size_t(1) << logN;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += size_t(gridDim.x) * blockDim.x) {
+    const uint64_t k1 = i >> LW, e = i & ((size_t(1) << LW) - 1);
+    const uint32_t ex = (uint32_t)((k1 * e) & (N - 1));
+    ztw[i] = tw_pow(tw.fwd_lo, tw.fwd_hi, ex << (TW_LOG - logN));
+  }
+}
+
 __global__ void k_fill_pattern(uint64_t *__restrict__ x, size_t n) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     x[i] = (i * 0x9E3779B97F4A7C15ull) >> 1;  // below 2^63 < p
@@ -41,9 +51,11 @@ __global__ void k_fill_pattern(uint64_t *__restrict__ x, size_t n) {
 
 }  // namespace
 
+static size_t twiddle_words() { return 4 * (size_t(1) << TW_HALF) + 2 * 8 * size_t(BFLY_ROWS); }
+
 v3db_status build_twiddles(v3db_ctx *ctx) {
   const size_t half = size_t(1) << TW_HALF;
-  std::vector<uint64_t> host(4 * half + 2 * DFT_N);
+  std::vector<uint64_t> host(twiddle_words());
   const uint64_t w = gl::root_of_unity(TW_LOG), wi = gl::inv(w);
   const uint64_t wstep = gl::pow(w, half), wistep = gl::pow(wi, half);
   uint64_t a = 1, b = 1, c = 1, d = 1;
@@ -51,11 +63,18 @@ v3db_status build_twiddles(v3db_ctx *ctx) {
     host[i] = a, host[half + i] = b, host[2 * half + i] = c, host[3 * half + i] = d;
     a = gl::mul(a, w), b = gl::mul(b, wstep), c = gl::mul(c, wi), d = gl::mul(d, wistep);
   }
-  const uint64_t w4 = gl::root_of_unity(DFT_LOG_MAX), w4i = gl::inv(w4);
-  a = 1, c = 1;
-  for (int t = 0; t < DFT_N; t++) {
-    host[4 * half + t] = a, host[4 * half + DFT_N + t] = c;
-    a = gl::mul(a, w4), c = gl::mul(c, w4i);
+  // butterfly rows: for S = 2^logS, row i holds w_S^(i * bitrev3(j)), j < 8
+  uint64_t *bf = host.data() + 4 * half, *bi = bf + 8 * size_t(BFLY_ROWS);
+  for (int logS = 3; logS <= DFT_LOG_MAX; logS++) {
+    const uint64_t ws = gl::root_of_unity(logS), wsi = gl::inv(ws);
+    for (int i = 0; i < (1 << (logS - 3)); i++) {
+      const size_t row = 8 * size_t(bfly_row0(logS) + i);
+      for (int j = 0; j < 8; j++) {
+        const int r = ((j & 1) << 2) | (j & 2) | (j >> 2);
+        bf[row + j] = gl::pow(ws, uint64_t(i) * r);
+        bi[row + j] = gl::pow(wsi, uint64_t(i) * r);
+      }
+    }
   }
   uint64_t *buf = nullptr;
   v3db_status st = ctx_alloc(ctx, (void **)&buf, host.size() * 8, "twiddle tables");
@@ -64,15 +83,15 @@ v3db_status build_twiddles(v3db_ctx *ctx) {
   ctx->tw.fwd_hi = buf + half;
   ctx->tw.inv_lo = buf + 2 * half;
   ctx->tw.inv_hi = buf + 3 * half;
-  ctx->tw.dft_fwd = buf + 4 * half;
-  ctx->tw.dft_inv = buf + 4 * half + DFT_N;
+  ctx->tw.bfly_fwd = buf + 4 * half;
+  ctx->tw.bfly_inv = buf + 4 * half + 8 * size_t(BFLY_ROWS);
   return hip_check(hipMemcpy(buf, host.data(), host.size() * 8, hipMemcpyHostToDevice), "upload twiddles");
 }
 
 static void free_plan(v3db_ctx *ctx, LdePlan &p);
 
 void free_twiddles(v3db_ctx *ctx) {
-  if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, (4 * (size_t(1) << TW_HALF) + 2 * DFT_N) * 8);
+  if (ctx->tw.fwd_lo) ctx_free(ctx, ctx->tw.fwd_lo, twiddle_words() * 8);
   ctx->tw = Twiddles{};
   for (auto &kv : ctx->plans) free_plan(ctx, kv.second);
   ctx->plans.clear();
@@ -139,13 +158,31 @@ static v3db_status build_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blo
   }
   p.d_twist = buf;
   p.d_scale = buf + B * n2;
+  p.d_ztw = nullptr;
+  const uint32_t logN = log_rows + log_blowup;
+  if (logN <= ZTW_MAX_LOG) {
+    const size_t N = size_t(1) << logN;
+    st = ctx_alloc(ctx, (void **)&p.d_ztw, N * 8, "LDE twiddle table");
+    if (st == V3DB_OK) {
+      const unsigned blocks = (unsigned)std::min<size_t>((N + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_fill_ztw, dim3(blocks), dim3(256), 0, nullptr, p.d_ztw, (int)(p.L2 + log_blowup),
+                         (int)logN, ctx->tw);
+      st = hip_check(hipGetLastError(), "fill LDE twiddle table");
+      if (st == V3DB_OK) st = hip_check(hipStreamSynchronize(nullptr), "fill LDE twiddle table");
+    }
+    if (st != V3DB_OK) {
+      free_plan(ctx, p);
+      return st;
+    }
+  }
   return V3DB_OK;
 }
 
 static void free_plan(v3db_ctx *ctx, LdePlan &p) {
   const size_t bytes = ((size_t(1) << (p.L2 + p.log_blowup)) + (size_t(1) << p.L1)) * 8;
   ctx_free(ctx, p.d_twist, bytes);
-  p.d_twist = p.d_scale = nullptr;
+  if (p.d_ztw) ctx_free(ctx, p.d_ztw, (size_t(1) << (p.log_rows + p.log_blowup)) * 8);
+  p.d_twist = p.d_scale = p.d_ztw = nullptr;
 }
 
 void drop_plans(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup) {
@@ -200,6 +237,7 @@ LdeTask lde_task(const LdePlan &plan, const uint64_t *trace, uint64_t *y, uint64
   s.lde = lde;
   s.twist = plan.d_twist;
   s.scale = plan.d_scale;
+  s.ztw = plan.d_ztw;
   s.L = (int)plan.log_rows;
   s.b = (int)plan.log_blowup;
   s.L1 = (int)plan.L1;

@@ -44,6 +44,21 @@ __global__ void __launch_bounds__(THREADS) k_merkle_level(const uint64_t *__rest
   merkle_node(below, k, above + k * DIGEST, rc, a);
 }
 
+// One level with few nodes: 16 lanes per node (wide_permute).
+__global__ void __launch_bounds__(WIDE_THREADS) k_merkle_level_wide(const uint64_t *__restrict__ below,
+                                                                    uint64_t *__restrict__ above, uint64_t count,
+                                                                    const uint64_t *__restrict__ rc,
+                                                                    const uint32_t *__restrict__ circ_rows) {
+  __shared__ uint64_t xs[2 * WIDE_THREADS];
+  const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
+  const uint64_t k = uint64_t(blockIdx.x) * WIDE_PER_BLOCK + grp;
+  const bool live = k < count;
+  uint64_t s = 0;
+  if (live && g < 2 * DIGEST) s = below[k * 2 * DIGEST + g];
+  s = wide_permute(s, g, grp, xs, rc, circ_rows);
+  if (live && g < DIGEST) above[k * DIGEST + g] = gl::canon(s);
+}
+
 inline unsigned blocks_for(uint64_t n) { return (unsigned)((n + THREADS - 1) / THREADS); }
 
 }  // namespace
@@ -68,8 +83,13 @@ v3db_status enqueue_merkle_levels(v3db_ctx *ctx, uint64_t *tree, uint32_t log_le
   uint64_t off = 0, cnt = uint64_t(1) << log_leaves;
   for (uint32_t lvl = log_leaves; lvl > cap_height; lvl--) {
     const uint64_t above = cnt / 2;
-    hipLaunchKernelGGL(k_merkle_level, dim3(blocks_for(above)), dim3(THREADS), 0, stream, tree + off * DIGEST,
-                       tree + (off + cnt) * DIGEST, above, ctx->d_pos, c);
+    if (above <= MERKLE_WIDE_MAX_NODES)
+      hipLaunchKernelGGL(k_merkle_level_wide, dim3((unsigned)((above + WIDE_PER_BLOCK - 1) / WIDE_PER_BLOCK)),
+                         dim3(WIDE_THREADS), 0, stream, tree + off * DIGEST, tree + (off + cnt) * DIGEST, above,
+                         ctx->d_pos, ctx->d_circ_rows);
+    else
+      hipLaunchKernelGGL(k_merkle_level, dim3(blocks_for(above)), dim3(THREADS), 0, stream, tree + off * DIGEST,
+                         tree + (off + cnt) * DIGEST, above, ctx->d_pos, c);
     off += cnt;
     cnt = above;
   }

@@ -135,6 +135,49 @@ __device__ __forceinline__ void merkle_node(const uint64_t *__restrict__ below, 
   for (int i = 0; i < DIGEST; i++) out[i] = gl::canon(s[i]);
 }
 
+// Permutation by a group of 16 lanes, lane g < 12 holding state word g (lanes
+// 12..15 follow lane 0 and are discarded). Each round applies the S-box on the
+// lane's own word (full rounds) or on lane 0 (partial rounds), then the lanes
+// exchange their words through LDS and each forms its own row of the matrix
+// product. The dependent chain per permutation is about a quarter of the
+// one-permutation-per-lane form, which is what the upper tree levels (too few
+// nodes to fill the device) are bound by. xs is a block-wide buffer of
+// 2 * WIDE_THREADS words (double-buffered, so one barrier per round suffices);
+// every lane of the block must call this (it contains barriers).
+constexpr int WIDE_GROUP = 16;
+constexpr int WIDE_THREADS = 64;  // one wave: 4 permutations
+constexpr int WIDE_PER_BLOCK = WIDE_THREADS / WIDE_GROUP;
+
+__device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, int grp, uint64_t *xs,
+                                                 const uint64_t *__restrict__ rc,
+                                                 const uint32_t *__restrict__ circ_rows) {
+  const int gi = g < WIDTH ? g : 0;
+  uint32_t m[WIDTH];  // this lane's row of the matrix
+#pragma unroll
+  for (int j = 0; j < WIDTH; j++) m[j] = circ_rows[gi * WIDTH + j];
+  s = gl::add_r(s, rc[gi]);
+  uint64_t rcn = rc[WIDTH + gi];
+#pragma unroll 1
+  for (int r = 0; r < ROUNDS; r++) {
+    const uint64_t rc_next = rcn;
+    if (r + 1 < ROUNDS) rcn = rc[(r + 2) * WIDTH + gi];
+    const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
+    if (full || g == 0) s = sbox(s);
+    uint64_t *buf = xs + (r & 1) * WIDE_THREADS + grp * WIDE_GROUP;
+    buf[g] = s;
+    __syncthreads();
+    uint64_t al = (uint32_t)rc_next, ah = rc_next >> 32;
+#pragma unroll
+    for (int j = 0; j < WIDTH; j++) {
+      const uint64_t v = buf[j];
+      al += (uint64_t)m[j] * (uint32_t)v;
+      ah += (uint64_t)m[j] * (uint32_t)(v >> 32);
+    }
+    s = fold(al, ah);
+  }
+  return s;
+}
+
 inline Circ circ_of(const v3db_ctx *ctx) {
   Circ c;
   for (int i = 0; i < WIDTH; i++) c.a[i] = ctx->pos.circ[i];
