@@ -344,20 +344,20 @@ v3db_status autotune_lde(v3db_ctx *ctx, uint32_t L, uint32_t b, uint32_t n_cols,
   };
   // coordinate search: the split, then each pass's tile cap, then the column chunk
   const LdeSchedule d = best;
-  for (int delta : {-2, -1, 1, 2}) {
+  for (int delta : {-3, -2, -1, 1, 2, 3}) {
     LdeSchedule c = d;
     if ((int)c.L2 + delta < 0) continue;
     c.L2 = (uint32_t)((int)c.L2 + delta);
     consider(c);
   }
   for (int pass = 1; pass <= 3; pass++)
-    for (uint32_t cap : {2u, 3u}) {
+    for (uint32_t cap : {0u, 1u, 2u, 3u}) {
       LdeSchedule c = best;
       (pass == 1 ? c.cap1 : pass == 2 ? c.cap2 : c.cap3) = cap;
       consider(c);
     }
   if (n_cols > 1)
-    for (uint32_t ch : {4u, 16u}) {
+    for (uint32_t ch : {2u, 4u, 16u}) {
       LdeSchedule c = best;
       c.chunk = ch;
       consider(c);

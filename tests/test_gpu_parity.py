@@ -118,6 +118,19 @@ def test_merkle_commit(v3db, ctx, poseidon, n_cols, log_leaves, cap_height):
     assert np.array_equal(_host(v3db, cap2), ocap)
 
 
+@pytest.mark.parametrize("log_leaves,cap_height", [(16, 0), (17, 3)])
+def test_merkle_commit_across_wide_threshold(v3db, ctx, poseidon, log_leaves, cap_height):
+    """Trees whose lower levels run one node per lane and whose levels of at most
+    2^15 nodes run 16 lanes per node: the whole tree against the oracle."""
+    import torch
+    mat = inputs.trace(15, log_leaves, 4, log_leaves)
+    tree = torch.empty(((2 << log_leaves) - (1 << cap_height), 4), dtype=torch.int64, device="cuda")
+    cap = ctx.merkle_commit(_dev(v3db, mat), cap_height, tree=tree)
+    ocap, otree = poseidon.merkle_commit(mat, cap_height, want_tree=True)
+    assert np.array_equal(_host(v3db, tree), otree)
+    assert np.array_equal(_host(v3db, cap), ocap)
+
+
 # ------------------------------------------------------------------- commit
 
 def _commit_one(v3db, ctx, tr, log_blowup, shift, layout, cap_height, want_all=True):
