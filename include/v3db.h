@@ -175,6 +175,41 @@ v3db_status v3db_profile_read(v3db_ctx *ctx, double *ms_out, uint64_t *count_out
 typedef enum { V3DB_OPT_BATCHING = 0, V3DB_OPT_BATCH_GROUP_BYTES = 1 } v3db_option;
 v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value);
 
+/* ---------------------------------------------------------------- openings
+ * Audit on demand: after a commitment the prover answers challenged leaf indices
+ * with the committed rows and their Merkle authentication paths, and the verifier
+ * recomputes the cap entry from each (MerkleOpen, Sec. 4.4: walk from the leaf to
+ * the top, taking the node as left or right child by the bits of the index).
+ *
+ * v3db_open_batch gathers, for each of n_queries indices idx[q] (device array,
+ * each < 2^log_leaves):
+ *   d_rows  [n_queries][n_cols]: row idx[q] of the stored matrix d_mat
+ *           (column-major [n_cols][1 << log_leaves], the LDE as committed);
+ *   d_paths [n_queries][log_leaves - cap_height][4]: for level l = 0 (leaves) ..
+ *           log_leaves - cap_height - 1, the sibling of the node above leaf idx[q]
+ *           at that level, read from d_tree (the stored tree of v3db_merkle_commit
+ *           or v3db_commit_batch: [(2 << log_leaves) - (1 << cap_height)][4]).
+ * All pointers are device memory owned by the caller; d_paths may be NULL when
+ * log_leaves == cap_height. An index >= 2^log_leaves is a caller error: with
+ * V3DB_VALIDATE=1 it fails with INVALID_ARG before anything is enqueued,
+ * otherwise the index is taken modulo 2^log_leaves (nothing is read out of
+ * bounds). n_queries == 0 does nothing. Errors: INVALID_ARG (NULL pointer,
+ * n_cols == 0, cap_height > log_leaves), UNSUPPORTED (log_leaves > 26 or
+ * n_cols > 65535), DEVICE. */
+v3db_status v3db_open_batch(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
+                            const uint64_t *d_tree, uint32_t cap_height, const uint64_t *d_idx, size_t n_queries,
+                            uint64_t *d_rows, uint64_t *d_paths, v3db_stream stream);
+
+/* The verifier's side, batched: d_ok[q] = 1 if hashing row q (the rate-8 sponge of
+ * the commitment) and compressing up its path (layouts as v3db_open_batch) gives
+ * entry idx[q] >> (log_leaves - cap_height) of d_cap ([1 << cap_height][4]),
+ * else 0. Rows and paths may be any 64-bit words (a non-canonical word is treated
+ * as its residue, so a tampered opening fails only if it changes the value mod p);
+ * indices as v3db_open_batch. Errors as v3db_open_batch. */
+v3db_status v3db_verify_batch(v3db_ctx *ctx, const uint64_t *d_rows, uint32_t n_cols, uint32_t log_leaves,
+                              uint32_t cap_height, const uint64_t *d_idx, size_t n_queries, const uint64_t *d_paths,
+                              const uint64_t *d_cap, uint32_t *d_ok, v3db_stream stream);
+
 /* ---------------------------------------------------------------- schedules
  * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
  * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):

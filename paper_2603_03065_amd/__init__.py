@@ -165,6 +165,8 @@ def lib():
         "v3db_server_destroy": (None, [vp]),
         "v3db_profile_read": (i32, [vp, vp, vp]),
         "v3db_autotune_lde": (i32, [vp, u32, u32, u32, i32, ctypes.POINTER(_Schedule)]),
+        "v3db_open_batch": (i32, [vp, vp, u32, u32, vp, u32, vp, sz, vp, vp, vp]),
+        "v3db_verify_batch": (i32, [vp, vp, u32, u32, u32, vp, sz, vp, vp, vp, vp]),
         "v3db_get_schedule": (i32, [vp, u32, u32, ctypes.POINTER(_Schedule)]),
         "v3db_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
         "v3db_schedules_save": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(sz)]),
@@ -300,6 +302,33 @@ class Context:
         _check(lib().v3db_merkle_commit(self._h, _ptr(mat), n_cols, log_leaves, cap_height, _ptr(tree), _ptr(cap),
                                         _stream(stream)))
         return cap
+
+    def open_batch(self, mat, tree, cap_height: int, idx, rows=None, paths=None, stream=None):
+        """Rows idx[q] of the committed matrix mat ([C][2^L]) and their authentication paths
+        ([Q][L - cap_height][4], leaf level first) from the stored tree."""
+        import torch
+        n_cols, nl = mat.shape
+        log_leaves = nl.bit_length() - 1
+        q = idx.numel()
+        if rows is None:
+            rows = torch.empty((q, n_cols), dtype=torch.int64, device=mat.device)
+        if paths is None:
+            paths = torch.empty((q, log_leaves - cap_height, 4), dtype=torch.int64, device=mat.device)
+        _check(lib().v3db_open_batch(self._h, _ptr(mat), n_cols, log_leaves, _ptr(tree), cap_height, _ptr(idx), q,
+                                     _ptr(rows), _ptr(paths) if paths.numel() else None, _stream(stream)))
+        return rows, paths
+
+    def verify_batch(self, rows, paths, idx, cap, log_leaves: int, cap_height: int, ok=None, stream=None):
+        """1 where row q and path q reproduce cap entry idx[q] >> (log_leaves - cap_height), else 0."""
+        import torch
+        q, n_cols = rows.shape
+        if ok is None:
+            ok = torch.empty((q,), dtype=torch.int32, device=rows.device)
+        assert ok.dtype == torch.int32 and ok.is_cuda and ok.is_contiguous()
+        _check(lib().v3db_verify_batch(self._h, _ptr(rows), n_cols, log_leaves, cap_height, _ptr(idx), q,
+                                       _ptr(paths) if paths.numel() else None, _ptr(cap), ok.data_ptr(),
+                                       _stream(stream)))
+        return ok
 
     @staticmethod
     def _jobs(jobs: Sequence[Job]):

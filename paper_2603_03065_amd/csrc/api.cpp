@@ -151,6 +151,46 @@ static v3db_status check_canonical(v3db_ctx *ctx, const uint64_t *x, size_t n, h
   return V3DB_OK;
 }
 
+// Optional index check (V3DB_VALIDATE=1): counts indices >= limit.
+__global__ void k_count_out_of_range(const uint64_t *__restrict__ x, size_t n, uint64_t limit, unsigned int *bad) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  unsigned int local = 0;
+  for (; i < n; i += stride) local += x[i] >= limit;
+  if (local) atomicAdd(bad, local);
+}
+
+static v3db_status check_indices(v3db_ctx *ctx, const uint64_t *idx, size_t n, uint64_t limit, hipStream_t stream) {
+  if (!validate_inputs_enabled() || n == 0) return V3DB_OK;
+  unsigned int *d_bad = nullptr;
+  v3db_status st = ctx_alloc(ctx, (void **)&d_bad, sizeof(unsigned int), "validation flag");
+  if (st != V3DB_OK) return st;
+  unsigned int bad = 0;
+  hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(unsigned int), stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_count_out_of_range, dim3(64), dim3(256), 0, stream, idx, n, limit, d_bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  ctx_free(ctx, d_bad, sizeof(unsigned int));
+  if (e != hipSuccess) return hip_check(e, "validation");
+  if (bad) return set_error(V3DB_ERR_INVALID_ARG, std::to_string(bad) + " query indices are >= 2^log_leaves");
+  return V3DB_OK;
+}
+
+static v3db_status check_open_args(const char *who, const void *a, const void *b, const void *c, uint32_t n_cols,
+                                   uint32_t log_leaves, uint32_t cap_height, size_t n_q, const void *paths) {
+  if (n_q && (!a || !b || !c)) return set_error(V3DB_ERR_INVALID_ARG, std::string(who) + ": NULL pointer");
+  if (n_q && log_leaves > cap_height && !paths)
+    return set_error(V3DB_ERR_INVALID_ARG, std::string(who) + ": NULL paths");
+  if (n_cols == 0) return set_error(V3DB_ERR_INVALID_ARG, std::string(who) + ": n_cols must be > 0");
+  if (cap_height > log_leaves) return set_error(V3DB_ERR_INVALID_ARG, std::string(who) + ": cap_height > log_leaves");
+  if (log_leaves > V3DB_MAX_LOG_LDE) return set_error(V3DB_ERR_UNSUPPORTED, std::string(who) + ": log_leaves > 26");
+  if (n_cols > V3DB_MAX_COLS) return set_error(V3DB_ERR_UNSUPPORTED, std::string(who) + ": more than 65535 columns");
+  return V3DB_OK;
+}
+
 }  // namespace v3db
 
 using namespace v3db;
@@ -472,6 +512,41 @@ v3db_status v3db_schedules_load(v3db_ctx *ctx, const char *path, size_t *count) 
   fclose(f);
   if (count) *count = k;
   return st;
+}
+
+
+v3db_status v3db_open_batch(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
+                            const uint64_t *d_tree, uint32_t cap_height, const uint64_t *d_idx, size_t n_queries,
+                            uint64_t *d_rows, uint64_t *d_paths, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "open_batch: NULL ctx");
+  v3db_status st = check_open_args("open_batch", d_mat, d_tree, d_idx, n_cols, log_leaves, cap_height, n_queries,
+                                   d_paths);
+  if (st == V3DB_OK && n_queries && !d_rows) st = set_error(V3DB_ERR_INVALID_ARG, "open_batch: NULL rows");
+  if (st != V3DB_OK || n_queries == 0) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  st = check_indices(ctx, d_idx, n_queries, uint64_t(1) << log_leaves, s);
+  if (st != V3DB_OK) return st;
+  return enqueue_open(ctx, d_mat, n_cols, log_leaves, d_tree, cap_height, d_idx, n_queries, d_rows, d_paths, s);
+}
+
+v3db_status v3db_verify_batch(v3db_ctx *ctx, const uint64_t *d_rows, uint32_t n_cols, uint32_t log_leaves,
+                              uint32_t cap_height, const uint64_t *d_idx, size_t n_queries, const uint64_t *d_paths,
+                              const uint64_t *d_cap, uint32_t *d_ok, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "verify_batch: NULL ctx");
+  v3db_status st = check_open_args("verify_batch", d_rows, d_cap, d_idx, n_cols, log_leaves, cap_height, n_queries,
+                                   d_paths);
+  if (st == V3DB_OK && n_queries && !d_ok) st = set_error(V3DB_ERR_INVALID_ARG, "verify_batch: NULL ok");
+  if (st != V3DB_OK || n_queries == 0) return st;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  st = check_indices(ctx, d_idx, n_queries, uint64_t(1) << log_leaves, s);
+  if (st != V3DB_OK) return st;
+  return enqueue_verify(ctx, d_rows, n_cols, log_leaves, cap_height, d_idx, n_queries, d_paths, d_cap, d_ok, s);
 }
 
 }  // extern "C"

@@ -143,6 +143,12 @@ void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 // Batched commits (batch.hip). scratch (nullable) replaces the context's
 // per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+v3db_status enqueue_open(v3db_ctx *ctx, const uint64_t *lde, uint32_t n_cols, uint32_t log_leaves, const uint64_t *tree,
+                         uint32_t cap_height, const uint64_t *idx, size_t n_q, uint64_t *rows, uint64_t *paths,
+                         hipStream_t stream);
+v3db_status enqueue_verify(v3db_ctx *ctx, const uint64_t *rows, uint32_t n_cols, uint32_t log_leaves,
+                           uint32_t cap_height, const uint64_t *idx, size_t n_q, const uint64_t *paths,
+                           const uint64_t *cap, uint32_t *ok, hipStream_t stream);
 v3db_status commit_batch_impl(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, hipStream_t stream,
                               void *scratch, size_t scratch_bytes);
 

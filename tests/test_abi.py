@@ -93,3 +93,11 @@ def test_schedule_calls_reject_null_arguments_without_device(v3db):
     assert lib.v3db_set_schedule(None, ctypes.byref(s)) == 1
     assert lib.v3db_schedules_save(None, b"/dev/null", None) == 1
     assert lib.v3db_schedules_load(None, b"/dev/null", None) == 1
+
+
+def test_open_and_verify_reject_bad_arguments_without_device(v3db):
+    lib = v3db.lib()
+    assert lib.v3db_open_batch(None, None, 1, 4, None, 0, None, 1, None, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
+    assert lib.v3db_verify_batch(None, None, 1, 4, 0, None, 1, None, None, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()

@@ -1,0 +1,152 @@
+"""GPU: openings of committed traces (rows and Merkle authentication paths of
+challenged leaves) against the oracle's LDE, tree and MerkleOpen, and the batched
+verifier: it accepts every honest opening and rejects tampered ones."""
+import numpy as np
+import pytest
+
+from paper_2603_03065_amd import inputs
+
+pytestmark = pytest.mark.gpu
+P = inputs.P
+
+
+@pytest.fixture(scope="module")
+def v3db():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2603_03065_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture()
+def ctx(v3db):
+    c = v3db.Context(0)
+    yield c
+    c.close()
+
+
+def _host(v3db, t):
+    import torch
+    torch.cuda.synchronize()
+    return v3db.to_host(t)
+
+
+def _ok(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().tolist()
+
+
+def _commit(v3db, ctx, tr, b, layout, h):
+    import torch
+    C, n = tr.shape
+    N = n << b
+    job = v3db.Job(trace=v3db.to_device(tr), log_blowup=b, cap_height=h, layout=layout,
+                   lde=torch.empty((C, N), dtype=torch.int64, device="cuda"),
+                   tree=torch.empty((2 * N - (1 << h), 4), dtype=torch.int64, device="cuda"))
+    ctx.commit(job)
+    return job
+
+
+def _indices(N, q, seed):
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, N, q).astype(np.uint64)
+    idx[:2] = [0, N - 1]
+    return idx
+
+
+@pytest.mark.parametrize("C,L,b,layout,h", [(8, 9, 3, 0, 0), (13, 7, 3, 1, 2), (3, 5, 2, 0, 7), (80, 6, 3, 0, 4),
+                                            (1, 0, 3, 0, 1), (9, 4, 1, 1, 5)])
+def test_openings_match_oracle(v3db, ctx, oracle_mod, poseidon, C, L, b, layout, h):
+    tr = inputs.trace(21, L, C, L)
+    N = 1 << (L + b)
+    job = _commit(v3db, ctx, tr, b, layout, h)
+    ocap, olde, otree = poseidon.commit(tr, b, 7, layout, h, want_lde=True, want_tree=True)
+    idx = _indices(N, 37, L)
+    rows, paths = ctx.open_batch(job.lde, job.tree, h, v3db.to_device(idx))
+    rows, paths = _host(v3db, rows), _host(v3db, paths)
+    for q, k in enumerate(idx):
+        k = int(k)
+        assert np.array_equal(rows[q], olde[:, k]), f"row of query {q} (leaf {k})"
+        assert np.array_equal(paths[q], oracle_mod.merkle_path(otree, L + b, h, k)), f"path of query {q}"
+        node, ci = poseidon.merkle_open(poseidon.sponge_state(olde[:, k])[:4], k, paths[q])
+        assert ci == k >> (L + b - h) and np.array_equal(node, ocap[ci])
+    ok = _ok(ctx.verify_batch(v3db.to_device(rows), v3db.to_device(paths), v3db.to_device(idx), job.cap, L + b, h))
+    assert ok == [1] * len(idx)
+
+
+def test_verifier_rejects_tampering(v3db, ctx, poseidon):
+    C, L, b, h = 11, 8, 3, 3
+    tr = inputs.trace(22, 0, C, L)
+    tr[3, :] = 0  # a zero column: its LDE is zero, so P is a non-canonical representative of its words
+    N = 1 << (L + b)
+    job = _commit(v3db, ctx, tr, b, 0, h)
+    idx = _indices(N, 16, 5)
+    rows, paths = ctx.open_batch(job.lde, job.tree, h, v3db.to_device(idx))
+    rows, paths = _host(v3db, rows), _host(v3db, paths)
+    # query 0 honest; 1: one row element + 1; 2: last row element changed; 3: a path word changed at
+    # the lowest level; 4: at the top level; 5: wrong index (a different leaf claimed); 6: index
+    # bit flipped at the top path level (node taken on the wrong side); 7: a zero row word written
+    # as p, its non-canonical representative (same residue: still accepted)
+    r, pth, ix = rows.copy(), paths.copy(), idx.copy()
+    r[1, 0] = (int(r[1, 0]) + 1) % P
+    r[2, C - 1] = (int(r[2, C - 1]) + 5) % P
+    pth[3, 0, 2] = (int(pth[3, 0, 2]) + 1) % P
+    pth[4, -1, 0] = (int(pth[4, -1, 0]) + 1) % P
+    ix[5] = (int(ix[5]) + 1) % N
+    ix[6] = int(ix[6]) ^ (1 << (L + b - h - 1))
+    assert int(r[7, 3]) == 0
+    r[7, 3] = P
+    ok = _ok(ctx.verify_batch(v3db.to_device(r), v3db.to_device(pth), v3db.to_device(ix), job.cap, L + b, h))
+    assert ok == [1, 0, 0, 0, 0, 0, 0, 1] + [1] * 8
+
+
+def test_open_empty_and_cap_level_paths(v3db, ctx, poseidon):
+    import torch
+    tr = inputs.trace(23, 0, 4, 3)
+    job = _commit(v3db, ctx, tr, 3, 0, 6)  # cap height = log N: empty paths, cap = leaves
+    idx = v3db.to_device(np.arange(64, dtype=np.uint64))
+    rows, paths = ctx.open_batch(job.lde, job.tree, 6, idx)
+    assert paths.shape == (64, 0, 4)
+    assert _ok(ctx.verify_batch(rows, paths, idx, job.cap, 6, 6)) == [1] * 64
+    # no queries: nothing to do
+    e = torch.empty((0,), dtype=torch.int64, device="cuda")
+    r0, p0 = ctx.open_batch(job.lde, job.tree, 6, e)
+    assert r0.shape == (0, 4)
+
+
+def test_index_validation(v3db, ctx, monkeypatch):
+    tr = inputs.trace(24, 0, 2, 4)
+    job = _commit(v3db, ctx, tr, 3, 0, 0)
+    monkeypatch.setenv("V3DB_VALIDATE", "1")
+    with pytest.raises(v3db.V3dbError, match="query indices"):
+        ctx.open_batch(job.lde, job.tree, 0, v3db.to_device(np.array([3, 1 << 7], dtype=np.uint64)))
+
+
+def test_fullsize_openings_80x2p18(v3db, ctx, oracle_mod, poseidon):
+    """Openings of the 80 x 2^18 -> 2^21 commitment (cap height 4): every opened row
+    against the oracle's interpolants evaluated at the leaf's coset point, and every
+    path accepted by the oracle's MerkleOpen from the oracle's leaf digest."""
+    import torch
+    oracle_mod.set_threads(0)
+    C, L, b, h = 80, 18, 3, 4
+    tr = inputs.trace(2, 0, C, L)
+    logN = L + b
+    N = 1 << logN
+    job = _commit(v3db, ctx, tr, b, 0, h)
+    idx = _indices(N, 24, 99)
+    rows, paths = ctx.open_batch(job.lde, job.tree, h, v3db.to_device(idx))
+    ok = _ok(ctx.verify_batch(rows, paths, v3db.to_device(idx), job.cap, logN, h))
+    rows, paths, cap = _host(v3db, rows), _host(v3db, paths), _host(v3db, job.cap)
+    del job
+    torch.cuda.empty_cache()
+    coeffs = oracle_mod.interpolate(tr)
+    wN = oracle_mod.root_of_unity(logN)
+    vals = oracle_mod.eval_columns(coeffs, [7 * pow(wN, int(k), P) % P for k in idx])
+    for q, k in enumerate(idx):
+        k = int(k)
+        assert np.array_equal(rows[q], vals[:, q]), f"row {k}"
+        node, ci = poseidon.merkle_open(poseidon.sponge_state(vals[:, q])[:4], k, paths[q])
+        assert ci == k >> (logN - h) and np.array_equal(node, cap[ci]), f"path {k}"
+    assert ok == [1] * len(idx)
