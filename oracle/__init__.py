@@ -82,6 +82,8 @@ def _load():
         "or_merkle_path": (i32, [_U64P, u32, u32, u64, _U64P]),
         "or_merkle_open": (None, [pp, _U64P, u64, _U64P, u32, _U64P, ctypes.POINTER(u64)]),
         "or_commit": (i32, [pp, _U64P, u32, u32, u32, u64, i32, u32, _U64P, _U64P, _U64P]),
+        "or_snapshot_commit": (i32, [pp, u32, u32, u32, u32, u32, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P,
+                                     _U64P, _U64P]),
         "or_set_threads": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -224,6 +226,23 @@ class Poseidon:
         out = np.zeros(WIDTH, dtype=np.uint64)
         _load().or_compress_state(ctypes.byref(self._p), _ptr(l), _ptr(r), _ptr(out))
         return out
+
+    def snapshot_commit(self, log_lists: int, log_slots: int, m: int, dim: int, k: int, flag, item, codes,
+                        centroids, codebooks):
+        """Sec. 4.3 snapshot commitment: returns (root_mk, root_cb, list_roots, list_hashes).
+        flag, item: [N]; codes: [M][N]; centroids: [n_list][D]; codebooks: [M][K][D/M]
+        (canonical flattening), N = n_list * n."""
+        n_list = 1 << log_lists
+        args = [_u64(a).reshape(-1) for a in (flag, item, codes, centroids, codebooks)]
+        roots = np.empty((n_list, DIGEST), dtype=np.uint64)
+        hashes = np.empty((n_list, DIGEST), dtype=np.uint64)
+        mk = np.empty(DIGEST, dtype=np.uint64)
+        cb = np.empty(DIGEST, dtype=np.uint64)
+        rc = _load().or_snapshot_commit(ctypes.byref(self._p), log_lists, log_slots, m, dim, k,
+                                        *[_ptr(a) for a in args], _ptr(roots), _ptr(hashes), _ptr(mk), _ptr(cb))
+        if rc != 0:
+            raise ValueError("oracle snapshot_commit: invalid arguments")
+        return mk, cb, roots, hashes
 
     def leaf_digests(self, mat: np.ndarray) -> np.ndarray:
         m = _u64(mat)

@@ -415,6 +415,86 @@ int or_commit(const or_poseidon_params *pp, const uint64_t *trace, uint32_t n_co
   return rc;
 }
 
+/* MerkleTree over 2^log_leaves given digests: pairs compressed level by level down
+ * to one root. */
+static void merkle_root_of(const or_poseidon_params *pp, const uint64_t *leaves, uint32_t log_leaves,
+                           uint64_t root[OR_DIGEST]) {
+  uint64_t cnt = 1ULL << log_leaves;
+  uint64_t *cur = (uint64_t *)malloc(sizeof(uint64_t) * OR_DIGEST * cnt);
+  memcpy(cur, leaves, sizeof(uint64_t) * OR_DIGEST * cnt);
+  while (cnt > 1) {
+    for (uint64_t k = 0; k < cnt / 2; k++) {
+      uint64_t st[OR_WIDTH];
+      or_compress_state(pp, cur + 2 * k * OR_DIGEST, cur + (2 * k + 1) * OR_DIGEST, st);
+      memcpy(cur + k * OR_DIGEST, st, sizeof(uint64_t) * OR_DIGEST);
+    }
+    cnt /= 2;
+  }
+  memcpy(root, cur, sizeof(uint64_t) * OR_DIGEST);
+  free(cur);
+}
+
+int or_snapshot_commit(const or_poseidon_params *pp, uint32_t log_lists, uint32_t log_slots, uint32_t m,
+                       uint32_t dim, uint32_t k, const uint64_t *flag, const uint64_t *item,
+                       const uint64_t *codes, const uint64_t *centroids, const uint64_t *codebooks,
+                       uint64_t *list_roots, uint64_t *list_hashes, uint64_t root_mk[OR_DIGEST],
+                       uint64_t root_cb[OR_DIGEST]) {
+  if (!pp || !flag || !item || !codes || !centroids || !codebooks || !root_mk || !root_cb) return -1;
+  if (m == 0 || k == 0 || dim % m != 0 || log_lists + log_slots > 30) return -1;
+  const uint64_t n_list = 1ULL << log_lists, n = 1ULL << log_slots, N = n_list * n;
+  /* leaf digests hash_{i,j}, record order (list-major) */
+  uint64_t *leaf = (uint64_t *)malloc(sizeof(uint64_t) * OR_DIGEST * N);
+  uint64_t *roots = (uint64_t *)malloc(sizeof(uint64_t) * OR_DIGEST * n_list);
+  uint64_t *hashes = (uint64_t *)malloc(sizeof(uint64_t) * OR_DIGEST * n_list);
+  if (!leaf || !roots || !hashes) {
+    free(leaf), free(roots), free(hashes);
+    return -1;
+  }
+#pragma omp parallel
+  {
+    uint64_t *seq = (uint64_t *)malloc(sizeof(uint64_t) * (4 + m));
+#pragma omp for schedule(static)
+    for (int64_t t = 0; t < (int64_t)N; t++) {
+      uint64_t st[OR_WIDTH];
+      seq[0] = (uint64_t)t >> log_slots;          /* i */
+      seq[1] = (uint64_t)t & (n - 1);             /* j */
+      seq[2] = flag[t];
+      seq[3] = item[t];
+      for (uint32_t mm = 0; mm < m; mm++) seq[4 + mm] = codes[(uint64_t)mm * N + t];
+      or_sponge_state(pp, seq, 4 + m, st);
+      memcpy(leaf + (uint64_t)t * OR_DIGEST, st, sizeof(uint64_t) * OR_DIGEST);
+    }
+    free(seq);
+  }
+  /* list roots, then each centroid bound to its list root */
+#pragma omp parallel
+  {
+    uint64_t *seq = (uint64_t *)malloc(sizeof(uint64_t) * (1 + dim + OR_DIGEST));
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < (int64_t)n_list; i++) {
+      uint64_t st[OR_WIDTH];
+      merkle_root_of(pp, leaf + (uint64_t)i * n * OR_DIGEST, log_slots, roots + (uint64_t)i * OR_DIGEST);
+      seq[0] = (uint64_t)i;
+      memcpy(seq + 1, centroids + (uint64_t)i * dim, sizeof(uint64_t) * dim);
+      memcpy(seq + 1 + dim, roots + (uint64_t)i * OR_DIGEST, sizeof(uint64_t) * OR_DIGEST);
+      or_sponge_state(pp, seq, 1 + dim + OR_DIGEST, st);
+      memcpy(hashes + (uint64_t)i * OR_DIGEST, st, sizeof(uint64_t) * OR_DIGEST);
+    }
+    free(seq);
+  }
+  merkle_root_of(pp, hashes, log_lists, root_mk);
+  /* codebook digest over the canonical flattening (K*D elements) */
+  {
+    uint64_t st[OR_WIDTH];
+    or_sponge_state(pp, codebooks, (uint32_t)((uint64_t)k * dim), st);
+    memcpy(root_cb, st, sizeof(uint64_t) * OR_DIGEST);
+  }
+  if (list_roots) memcpy(list_roots, roots, sizeof(uint64_t) * OR_DIGEST * n_list);
+  if (list_hashes) memcpy(list_hashes, hashes, sizeof(uint64_t) * OR_DIGEST * n_list);
+  free(leaf), free(roots), free(hashes);
+  return 0;
+}
+
 int or_set_threads(int n) {
 #ifdef _OPENMP
   if (n > 0) omp_set_num_threads(n);

@@ -132,6 +132,27 @@ int or_commit(const or_poseidon_params *pp, const uint64_t *trace, uint32_t n_co
               uint32_t log_rows, uint32_t log_blowup, uint64_t shift, int layout,
               uint32_t cap_height, uint64_t *lde, uint64_t *tree, uint64_t *cap);
 
+/* ---- Snapshot commitment (Sec. 4.3 "Snapshot Commitments") ----
+ * A fixed-shape IVF-PQ snapshot: n_list = 2^log_lists inverted lists of n = 2^log_slots
+ * slots; slot (i, j) is record t = i*n + j with validity flag flag[t], payload item[t]
+ * and M PQ codes codes[m*N + t] (N = n_list*n); centroid i is centroids[i*D .. i*D+D-1];
+ * the codebooks C_{m,k} (m < M, k < K, each of D/M coordinates) are given in their
+ * canonical flattening codebooks[(m*K + k)*(D/M) + c].
+ *   hash_{i,j} = Hash(i, j, f_ij, item_ij, v_ij^(0), ..., v_ij^(M-1))
+ *   root_i     = MerkleTree(hash_{i,0}, ..., hash_{i,n-1})
+ *   hash_i     = Hash(i, mu_i[0..D-1], root_i)
+ *   root_mk    = MerkleTree(hash_0, ..., hash_{n_list-1})
+ *   root_cb    = Hash(C_{0,0}, ..., C_{M-1,K-1})
+ * Hash is the rate-8 overwrite sponge (digest = lanes 0..3), MerkleTree the binary tree
+ * of Compress to a single root. list_roots [n_list][4] and list_hashes [n_list][4] are
+ * nullable outputs. Returns 0, or -1 on invalid arguments (M = 0, D not a multiple of M,
+ * K = 0, log_lists + log_slots > 30). */
+int or_snapshot_commit(const or_poseidon_params *pp, uint32_t log_lists, uint32_t log_slots, uint32_t m,
+                       uint32_t dim, uint32_t k, const uint64_t *flag, const uint64_t *item,
+                       const uint64_t *codes, const uint64_t *centroids, const uint64_t *codebooks,
+                       uint64_t *list_roots, uint64_t *list_hashes, uint64_t root_mk[OR_DIGEST],
+                       uint64_t root_cb[OR_DIGEST]);
+
 /* Threads used by the parallel loops (OpenMP); 0 leaves the default. Returns the count in use. */
 int or_set_threads(int n);
 

@@ -70,3 +70,38 @@ def batch_shapes(n_traces: int = 64, stream: int = BATCH_SHAPE_STREAM):
 def uniform01(stream: int, i) -> np.ndarray:
     """Uniform doubles in [0, 1) from the top 53 bits of SplitMix64(stream, i)."""
     return (splitmix64(stream, i) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+# ---- IVF-PQ snapshots ----------------------------------------------------------
+
+def _fixed_point(seed: int, kind: int, count: int) -> np.ndarray:
+    """count signed 16-bit fixed-point coordinates in the field: magnitude uniform in
+    [0, 2^16 - 1], negative values as p - |v| (the paper's encoding scales every
+    coordinate into [-(2^16 - 1), 2^16 - 1])."""
+    z = splitmix64(seed, (np.uint64(kind) << np.uint64(56)) | np.arange(count, dtype=np.uint64))
+    mag = z & np.uint64(0xFFFF)
+    neg = ((z >> np.uint64(16)) & np.uint64(1)).astype(bool) & (mag != 0)
+    return np.where(neg, np.uint64(P) - mag, mag)
+
+
+def snapshot(seed: int, log_lists: int, log_slots: int, m: int, dim: int, k: int):
+    """A synthetic fixed-shape IVF-PQ snapshot: n_list = 2^log_lists lists of
+    n = 2^log_slots slots, each list holding count_i valid records (uniform in
+    [3n/4, n], the rest padding), M PQ codes per record, D-dimensional centroids
+    and M x K codebooks of D/M coordinates.
+    Returns dict(flag [N], item [N], codes [M][N], centroids [n_list][D],
+    codebooks [M][K][D/M]) with records in list-major order (t = i * n + j)."""
+    n_list, n = 1 << log_lists, 1 << log_slots
+    N = n_list * n
+    cnt = splitmix64(seed, (np.uint64(1) << np.uint64(56)) | np.arange(n_list, dtype=np.uint64))
+    counts = n - (cnt % np.uint64(n // 4 + 1)).astype(np.int64)
+    j = np.tile(np.arange(n, dtype=np.int64), n_list)
+    valid = j < np.repeat(counts, n)
+    flag = valid.astype(np.uint64)
+    rid = splitmix64(seed, (np.uint64(2) << np.uint64(56)) | np.arange(N, dtype=np.uint64)) >> np.uint64(24)
+    item = np.where(valid, rid + np.uint64(1), np.uint64(0))
+    z = splitmix64(seed, (np.uint64(3) << np.uint64(56)) | np.arange(m * N, dtype=np.uint64)).reshape(m, N)
+    codes = np.where(valid[None, :], z % np.uint64(k), np.uint64(0))
+    centroids = _fixed_point(seed, 4, n_list * dim).reshape(n_list, dim)
+    codebooks = _fixed_point(seed, 5, k * dim).reshape(m, k, dim // m)
+    return {"flag": flag, "item": item, "codes": codes, "centroids": centroids, "codebooks": codebooks}
