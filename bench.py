@@ -37,6 +37,11 @@ WORKLOADS = {
 }
 BATCH_WORKLOAD = "commit-batch-64"   # 64 traces: log rows U{10..18}, cols U[20,135], blowup 8, cap 2
 OPEN_WORKLOAD = "open-8192"          # 8192 openings (rows + paths) of the 80 x 2^18 commitment, and their check
+SNAPSHOT_WORKLOADS = {
+    # name: (description, log_lists, log_slots, M, D, K, data seed)
+    "snapshot-sift1m": ("SIFT1M zk-opt layout: 1024 lists x 2048 slots (N = 2^21), M = 8, D = 128, K = 256", 10, 11, 8, 128, 256, 6),
+    "snapshot-gist1m": ("GIST1M zk-opt layout: 512 lists x 4096 slots (N = 2^21), M = 8, D = 960, K = 256", 9, 12, 8, 960, 256, 7),
+}
 DEFAULT_WORKLOAD = "commit-80x2^18"
 
 # Peaks of one MI355X (gfx950): 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU
@@ -78,7 +83,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
-                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, "serve-poisson", OPEN_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, "serve-poisson", OPEN_WORKLOAD] + sorted(SNAPSHOT_WORKLOADS))
     ap.add_argument("--serve-seconds", type=float, default=120.0)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -257,6 +262,60 @@ def open_main(args):
     print(json.dumps(out), flush=True)
 
 
+def snapshot_main(args):
+    """The paper's snapshot commitment comm = (root_mk, root_cb) of a synthetic
+    fixed-shape IVF-PQ snapshot resident in HBM: per step every record hashed, the
+    list trees, the centroid digests and their tree, and the codebook digest (a
+    sequential sponge on a side stream, overlapped with the rest)."""
+    import numpy as np
+    import torch
+
+    import paper_2603_03065_amd as v3db
+    from paper_2603_03065_amd import inputs
+
+    desc, ll, ls, m, dim, k, seed = SNAPSHOT_WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = inputs.snapshot(seed, ll, ls, m, dim, k)
+    d = {key: v3db.to_device(np.ascontiguousarray(v), dev) for key, v in s.items()}
+    ctx = v3db.Context(0)
+    stream = torch.cuda.current_stream(dev)
+    roots = torch.empty((1 << ll, 4), dtype=torch.int64, device=dev)
+    call = lambda: ctx.snapshot_commit(ll, ls, m, dim, k, d["flag"], d["item"], d["codes"], d["centroids"],
+                                       d["codebooks"], roots, stream)
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        call()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    N = 1 << (ll + ls)
+    chain = (k * dim + 7) // 8
+    perms = N * ((4 + m + 7) // 8) + (N - (1 << ll)) + (1 << ll) * ((1 + dim + 4 + 7) // 8) + ((1 << ll) - 1) + chain
+    out = {
+        "metric": "snapshot records committed per second at 1 GPU (comm = (root_mk, root_cb))",
+        "value": N * args.steps / wall,
+        "unit": "records/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}; records, centroids and codebooks resident in HBM",
+                   "records": N, "lists": 1 << ll, "M": m, "D": dim, "K": k},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "permutations_per_step": perms,
+        "codebook_chain_permutations": chain,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 SERVE_WORKLOAD = "serve-poisson"
 
 
@@ -395,6 +454,8 @@ def main():
         return serve_main(args)
     if args.workload == OPEN_WORKLOAD:
         return open_main(args)
+    if args.workload in SNAPSHOT_WORKLOADS:
+        return snapshot_main(args)
 
     import numpy as np
     import torch

@@ -210,6 +210,44 @@ v3db_status v3db_verify_batch(v3db_ctx *ctx, const uint64_t *d_rows, uint32_t n_
                               uint32_t cap_height, const uint64_t *d_idx, size_t n_queries, const uint64_t *d_paths,
                               const uint64_t *d_cap, uint32_t *d_ok, v3db_stream stream);
 
+/* ---------------------------------------------------------------- snapshot commitment
+ * The commitment comm = (root_mk, root_cb) of a fixed-shape IVF-PQ snapshot
+ * (Sec. 4.3 "Snapshot Commitments"): n_list = 2^log_lists inverted lists of
+ * n = 2^log_slots slots; record t = i*n + j (list i, slot j) has a validity flag,
+ * a payload and M PQ codes; each list has a D-dimensional centroid; the codebooks
+ * hold M x K vectors of D/M coordinates.
+ *   hash_{i,j} = Hash(i, j, flag_t, item_t, codes_t^(0), ..., codes_t^(M-1))
+ *   root_i     = MerkleTree(hash_{i,0}, ..., hash_{i,n-1})
+ *   hash_i     = Hash(i, centroid_i[0..D-1], root_i)
+ *   root_mk    = MerkleTree(hash_0, ..., hash_{n_list-1})
+ *   root_cb    = Hash(C_{0,0}, ..., C_{0,K-1}, C_{1,0}, ..., C_{M-1,K-1})
+ * Hash is the rate-8 overwrite sponge of the trace commitment (4-word digest),
+ * MerkleTree the same binary tree of Compress, down to one root. All arrays are
+ * device memory in the caller's ownership (u64 words, canonical field elements): */
+typedef struct {
+  uint32_t log_lists, log_slots;   /* n_list = 2^log_lists, n = 2^log_slots; sum <= 26 */
+  uint32_t m;                      /* PQ codes per record, >= 1 */
+  uint32_t dim;                    /* D, centroid dimension, a multiple of m */
+  uint32_t k;                      /* codebook size K, >= 1 */
+  const uint64_t *d_flag;          /* [N] validity flags, N = n_list * n, record order */
+  const uint64_t *d_item;          /* [N] payloads */
+  const uint64_t *d_codes;         /* [m][N] codes, one array per sub-quantizer */
+  const uint64_t *d_centroids;     /* [n_list][dim] */
+  const uint64_t *d_codebooks;     /* [m][k][dim/m], the canonical flattening */
+} v3db_snapshot;
+
+/* Enqueue the commitment on the stream: d_root_mk [4] and d_root_cb [4] receive
+ * the two roots, d_list_roots [n_list][4] (nullable) the list roots. The
+ * codebook digest is a sequential chain of K*D/8 permutations; it runs on an
+ * internal stream that waits for the caller's stream at the call and is waited
+ * for by it before anything enqueued later, so stream order is kept. Scratch:
+ * (3 n_list - 1 + 2N - n_list) digests from the context. Errors: INVALID_ARG (NULL
+ * pointer, m = 0, k = 0, dim not a multiple of m), UNSUPPORTED (log_lists +
+ * log_slots > 26, m > 65535, k * dim >= 2^32), NONCANONICAL (with V3DB_VALIDATE=1),
+ * OUT_OF_MEMORY, DEVICE. */
+v3db_status v3db_snapshot_commit(v3db_ctx *ctx, const v3db_snapshot *snap, uint64_t *d_list_roots,
+                                 uint64_t *d_root_mk, uint64_t *d_root_cb, v3db_stream stream);
+
 /* ---------------------------------------------------------------- schedules
  * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
  * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):

@@ -129,6 +129,21 @@ class Schedule:
                          self.chunk_cols, self.time_us)
 
 
+class _Snapshot(ctypes.Structure):
+    _fields_ = [
+        ("log_lists", ctypes.c_uint32),
+        ("log_slots", ctypes.c_uint32),
+        ("m", ctypes.c_uint32),
+        ("dim", ctypes.c_uint32),
+        ("k", ctypes.c_uint32),
+        ("d_flag", ctypes.c_void_p),
+        ("d_item", ctypes.c_void_p),
+        ("d_codes", ctypes.c_void_p),
+        ("d_centroids", ctypes.c_void_p),
+        ("d_codebooks", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -166,6 +181,7 @@ def lib():
         "v3db_profile_read": (i32, [vp, vp, vp]),
         "v3db_autotune_lde": (i32, [vp, u32, u32, u32, i32, ctypes.POINTER(_Schedule)]),
         "v3db_open_batch": (i32, [vp, vp, u32, u32, vp, u32, vp, sz, vp, vp, vp]),
+        "v3db_snapshot_commit": (i32, [vp, ctypes.POINTER(_Snapshot), vp, vp, vp, vp]),
         "v3db_verify_batch": (i32, [vp, vp, u32, u32, u32, vp, sz, vp, vp, vp, vp]),
         "v3db_get_schedule": (i32, [vp, u32, u32, ctypes.POINTER(_Schedule)]),
         "v3db_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
@@ -329,6 +345,23 @@ class Context:
                                        _ptr(paths) if paths.numel() else None, _ptr(cap), ok.data_ptr(),
                                        _stream(stream)))
         return ok
+
+    def snapshot_commit(self, log_lists: int, log_slots: int, m: int, dim: int, k: int, flag, item, codes,
+                        centroids, codebooks, list_roots=None, stream=None):
+        """Commitment (root_mk, root_cb) of a fixed-shape IVF-PQ snapshot held in device
+        tensors: flag, item [N]; codes [m][N]; centroids [n_list][dim]; codebooks
+        [m][k][dim/m]. Returns (root_mk [4], root_cb [4], list_roots [n_list][4])."""
+        import torch
+        dev = flag.device
+        if list_roots is None:
+            list_roots = torch.empty((1 << log_lists, 4), dtype=torch.int64, device=dev)
+        mk = torch.empty((4,), dtype=torch.int64, device=dev)
+        cb = torch.empty((4,), dtype=torch.int64, device=dev)
+        sn = _Snapshot(log_lists, log_slots, m, dim, k, _ptr(flag), _ptr(item), _ptr(codes), _ptr(centroids),
+                       _ptr(codebooks))
+        _check(lib().v3db_snapshot_commit(self._h, ctypes.byref(sn), _ptr(list_roots), _ptr(mk), _ptr(cb),
+                                          _stream(stream)))
+        return mk, cb, list_roots
 
     @staticmethod
     def _jobs(jobs: Sequence[Job]):

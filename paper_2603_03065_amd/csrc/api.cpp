@@ -243,6 +243,9 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_batch_graphs(ctx);
+  if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   prof_drop(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   ctx->event_pool.clear();
@@ -547,6 +550,35 @@ v3db_status v3db_verify_batch(v3db_ctx *ctx, const uint64_t *d_rows, uint32_t n_
   st = check_indices(ctx, d_idx, n_queries, uint64_t(1) << log_leaves, s);
   if (st != V3DB_OK) return st;
   return enqueue_verify(ctx, d_rows, n_cols, log_leaves, cap_height, d_idx, n_queries, d_paths, d_cap, d_ok, s);
+}
+
+
+v3db_status v3db_snapshot_commit(v3db_ctx *ctx, const v3db_snapshot *sn, uint64_t *d_list_roots,
+                                 uint64_t *d_root_mk, uint64_t *d_root_cb, v3db_stream stream) {
+  clear_error();
+  if (!ctx || !sn) return set_error(V3DB_ERR_INVALID_ARG, "snapshot_commit: NULL ctx or snapshot");
+  if (!sn->d_flag || !sn->d_item || !sn->d_codes || !sn->d_centroids || !sn->d_codebooks || !d_root_mk || !d_root_cb)
+    return set_error(V3DB_ERR_INVALID_ARG, "snapshot_commit: NULL array");
+  if (sn->m == 0 || sn->k == 0 || sn->dim == 0 || sn->dim % sn->m != 0)
+    return set_error(V3DB_ERR_INVALID_ARG, "snapshot_commit: need m >= 1, k >= 1 and dim a positive multiple of m");
+  if (sn->log_lists + sn->log_slots > V3DB_MAX_LOG_LDE || sn->m > 65535 || uint64_t(sn->k) * sn->dim >= (uint64_t(1) << 32))
+    return set_error(V3DB_ERR_UNSUPPORTED, "snapshot_commit: shape beyond the build limits");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n_list = size_t(1) << sn->log_lists, N = n_list << sn->log_slots;
+  v3db_status st = check_canonical(ctx, sn->d_flag, N, s);
+  if (st == V3DB_OK) st = check_canonical(ctx, sn->d_item, N, s);
+  if (st == V3DB_OK) st = check_canonical(ctx, sn->d_codes, N * sn->m, s);
+  if (st == V3DB_OK) st = check_canonical(ctx, sn->d_centroids, n_list * sn->dim, s);
+  if (st == V3DB_OK) st = check_canonical(ctx, sn->d_codebooks, size_t(sn->k) * sn->dim, s);
+  if (st != V3DB_OK) return st;
+  void *z = nullptr;
+  st = ctx_scratch(ctx, s, snapshot_scratch_words(sn->log_lists, sn->log_slots) * 8, &z);
+  if (st != V3DB_OK) return st;
+  return enqueue_snapshot(ctx, sn->log_lists, sn->log_slots, sn->m, sn->dim, sn->k, sn->d_flag, sn->d_item,
+                          sn->d_codes, sn->d_centroids, sn->d_codebooks, d_list_roots, d_root_mk, d_root_cb,
+                          (uint64_t *)z, s);
 }
 
 }  // extern "C"

@@ -93,6 +93,8 @@ struct v3db_ctx {
   std::vector<v3db::BatchGraph *> graphs;
   uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
+  hipStream_t side_stream = nullptr;  // snapshot codebook digest, forked from and joined into the caller's stream
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::mutex mu;
 };
 
@@ -143,6 +145,11 @@ void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 // Batched commits (batch.hip). scratch (nullable) replaces the context's
 // per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+size_t snapshot_scratch_words(uint32_t log_lists, uint32_t log_slots);
+v3db_status enqueue_snapshot(v3db_ctx *ctx, uint32_t log_lists, uint32_t log_slots, uint32_t m, uint32_t dim,
+                             uint32_t k, const uint64_t *flag, const uint64_t *item, const uint64_t *codes,
+                             const uint64_t *centroids, const uint64_t *codebooks, uint64_t *list_roots,
+                             uint64_t *root_mk, uint64_t *root_cb, uint64_t *scratch, hipStream_t stream);
 v3db_status enqueue_open(v3db_ctx *ctx, const uint64_t *lde, uint32_t n_cols, uint32_t log_leaves, const uint64_t *tree,
                          uint32_t cap_height, const uint64_t *idx, size_t n_q, uint64_t *rows, uint64_t *paths,
                          hipStream_t stream);

@@ -178,6 +178,21 @@ __device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, int grp, uin
   return s;
 }
 
+// Rate-8 overwrite sponge over a sequence of len words by a group of 16 lanes
+// (wide_permute); elem(x) gives word x and is called only by live lanes g < 8.
+// Lane g < 12 returns state word g.
+template <class Elem>
+__device__ __forceinline__ uint64_t wide_sponge(uint64_t len, bool live, Elem elem, int g, int grp, uint64_t *xs,
+                                                const uint64_t *__restrict__ rc,
+                                                const uint32_t *__restrict__ circ_rows) {
+  uint64_t s = 0;
+  for (uint64_t c0 = 0; c0 < len; c0 += RATE) {
+    if (live && g < RATE && c0 + g < len) s = elem(c0 + g);
+    s = wide_permute(s, g, grp, xs, rc, circ_rows);
+  }
+  return s;
+}
+
 inline Circ circ_of(const v3db_ctx *ctx) {
   Circ c;
   for (int i = 0; i < WIDTH; i++) c.a[i] = ctx->pos.circ[i];

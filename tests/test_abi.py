@@ -101,3 +101,9 @@ def test_open_and_verify_reject_bad_arguments_without_device(v3db):
     assert b"NULL ctx" in lib.v3db_last_error()
     assert lib.v3db_verify_batch(None, None, 1, 4, 0, None, 1, None, None, None, None) == 1
     assert b"NULL ctx" in lib.v3db_last_error()
+
+
+def test_snapshot_commit_rejects_bad_arguments_without_device(v3db):
+    lib = v3db.lib()
+    assert lib.v3db_snapshot_commit(None, None, None, None, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
