@@ -119,7 +119,6 @@ __global__ void __launch_bounds__(pos::WIDE_THREADS) k_batch_merkle_wide(const B
                                                                          int n_ranges, int depth,
                                                                          const uint64_t *__restrict__ rc,
                                                                          const uint32_t *__restrict__ circ_rows) {
-  __shared__ uint64_t xs[2 * pos::WIDE_THREADS];
   const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
   const BJob &j = jobs[r.job];
   const uint32_t level = j.logN - depth;
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(pos::WIDE_THREADS) k_batch_merkle_wide(const B
   const uint64_t off_here = (uint64_t(2) << j.logN) - (uint64_t(2) << level);
   uint64_t s = 0;
   if (live && g < 2 * DIGEST) s = j.tree[(off_below + 2 * k) * DIGEST + g];
-  s = pos::wide_permute(s, g, grp, xs, rc, circ_rows);
+  s = pos::wide_permute(s, g, rc, circ_rows);
   if (live && g < DIGEST) {
     const uint64_t v = gl::canon(s);
     j.tree[(off_here + k) * DIGEST + g] = v;

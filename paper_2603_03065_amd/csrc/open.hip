@@ -42,7 +42,6 @@ __global__ void __launch_bounds__(pos::WIDE_THREADS)
              const uint64_t *__restrict__ cap, uint32_t *__restrict__ ok, const uint64_t *__restrict__ rc,
              const uint32_t *__restrict__ circ_rows) {
   using namespace pos;
-  __shared__ uint64_t xs[2 * WIDE_THREADS];
   __shared__ uint64_t node[WIDE_PER_BLOCK][DIGEST];
   __shared__ uint32_t match[WIDE_PER_BLOCK][DIGEST];
   const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
@@ -54,7 +53,7 @@ __global__ void __launch_bounds__(pos::WIDE_THREADS)
   uint64_t s = 0;
   for (uint32_t c0 = 0; c0 < n_cols; c0 += RATE) {
     if (g < RATE && c0 + g < n_cols) s = live ? rows[q * n_cols + c0 + g] : 0;
-    s = wide_permute(s, g, grp, xs, rc, circ_rows);
+    s = wide_permute(s, g, rc, circ_rows);
   }
   for (uint32_t l = 0; l < depth; l++) {
     if (g < DIGEST) node[grp][g] = s;
@@ -64,7 +63,7 @@ __global__ void __launch_bounds__(pos::WIDE_THREADS)
     if (g < DIGEST) s = right ? (live ? sib[g] : 0) : node[grp][g];
     else if (g < 2 * DIGEST) s = right ? node[grp][g - DIGEST] : (live ? sib[g - DIGEST] : 0);
     else s = 0;
-    s = wide_permute(s, g, grp, xs, rc, circ_rows);
+    s = wide_permute(s, g, rc, circ_rows);
   }
   const uint64_t ci = index >> depth;
   if (g < DIGEST) match[grp][g] = live && gl::canon(s) == cap[ci * DIGEST + g];

@@ -49,13 +49,12 @@ __global__ void __launch_bounds__(WIDE_THREADS) k_merkle_level_wide(const uint64
                                                                     uint64_t *__restrict__ above, uint64_t count,
                                                                     const uint64_t *__restrict__ rc,
                                                                     const uint32_t *__restrict__ circ_rows) {
-  __shared__ uint64_t xs[2 * WIDE_THREADS];
   const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
   const uint64_t k = uint64_t(blockIdx.x) * WIDE_PER_BLOCK + grp;
   const bool live = k < count;
   uint64_t s = 0;
   if (live && g < 2 * DIGEST) s = below[k * 2 * DIGEST + g];
-  s = wide_permute(s, g, grp, xs, rc, circ_rows);
+  s = wide_permute(s, g, rc, circ_rows);
   if (live && g < DIGEST) above[k * DIGEST + g] = gl::canon(s);
 }
 

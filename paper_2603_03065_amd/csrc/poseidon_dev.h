@@ -137,19 +137,29 @@ __device__ __forceinline__ void merkle_node(const uint64_t *__restrict__ below, 
 
 // Permutation by a group of 16 lanes, lane g < 12 holding state word g (lanes
 // 12..15 follow lane 0 and are discarded). Each round applies the S-box on the
-// lane's own word (full rounds) or on lane 0 (partial rounds), then the lanes
-// exchange their words through LDS and each forms its own row of the matrix
-// product. The dependent chain per permutation is about a quarter of the
+// lane's own word (full rounds) or on lane 0 (partial rounds); then every lane
+// receives the 12 words by 64-bit row broadcasts (DPP row_newbcast: a group is
+// one 16-lane row) and forms its own row of the matrix product. The dependent chain per permutation is a fraction of the
 // one-permutation-per-lane form, which is what the upper tree levels (too few
-// nodes to fill the device) are bound by. xs is a block-wide buffer of
-// 2 * WIDE_THREADS words (double-buffered, so one barrier per round suffices);
-// every lane of the block must call this (it contains barriers).
+// nodes to fill the device) and long sequential sponges are bound by. All 64
+// lanes of the wave must be active when this is called.
 constexpr int WIDE_GROUP = 16;
 constexpr int WIDE_THREADS = 64;  // one wave: 4 permutations
 constexpr int WIDE_PER_BLOCK = WIDE_THREADS / WIDE_GROUP;
 
-__device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, int grp, uint64_t *xs,
-                                                 const uint64_t *__restrict__ rc,
+template <int J>
+__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
+  return (uint64_t)__builtin_amdgcn_update_dpp((long)0, (long)v, 0x150 + J, 0xf, 0xf, false);  // v_mov_b64_dpp
+}
+
+template <int J>
+__device__ __forceinline__ void mds_term(uint64_t s, const uint32_t m[WIDTH], uint64_t &al, uint64_t &ah) {
+  const uint64_t v = row_bcast<J>(s);
+  al += (uint64_t)m[J] * (uint32_t)v;
+  ah += (uint64_t)m[J] * (uint32_t)(v >> 32);
+}
+
+__device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, const uint64_t *__restrict__ rc,
                                                  const uint32_t *__restrict__ circ_rows) {
   const int gi = g < WIDTH ? g : 0;
   uint32_t m[WIDTH];  // this lane's row of the matrix
@@ -163,16 +173,19 @@ __device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, int grp, uin
     if (r + 1 < ROUNDS) rcn = rc[(r + 2) * WIDTH + gi];
     const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
     if (full || g == 0) s = sbox(s);
-    uint64_t *buf = xs + (r & 1) * WIDE_THREADS + grp * WIDE_GROUP;
-    buf[g] = s;
-    __syncthreads();
     uint64_t al = (uint32_t)rc_next, ah = rc_next >> 32;
-#pragma unroll
-    for (int j = 0; j < WIDTH; j++) {
-      const uint64_t v = buf[j];
-      al += (uint64_t)m[j] * (uint32_t)v;
-      ah += (uint64_t)m[j] * (uint32_t)(v >> 32);
-    }
+    mds_term<0>(s, m, al, ah);
+    mds_term<1>(s, m, al, ah);
+    mds_term<2>(s, m, al, ah);
+    mds_term<3>(s, m, al, ah);
+    mds_term<4>(s, m, al, ah);
+    mds_term<5>(s, m, al, ah);
+    mds_term<6>(s, m, al, ah);
+    mds_term<7>(s, m, al, ah);
+    mds_term<8>(s, m, al, ah);
+    mds_term<9>(s, m, al, ah);
+    mds_term<10>(s, m, al, ah);
+    mds_term<11>(s, m, al, ah);
     s = fold(al, ah);
   }
   return s;
@@ -182,13 +195,13 @@ __device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, int grp, uin
 // (wide_permute); elem(x) gives word x and is called only by live lanes g < 8.
 // Lane g < 12 returns state word g.
 template <class Elem>
-__device__ __forceinline__ uint64_t wide_sponge(uint64_t len, bool live, Elem elem, int g, int grp, uint64_t *xs,
+__device__ __forceinline__ uint64_t wide_sponge(uint64_t len, bool live, Elem elem, int g,
                                                 const uint64_t *__restrict__ rc,
                                                 const uint32_t *__restrict__ circ_rows) {
   uint64_t s = 0;
   for (uint64_t c0 = 0; c0 < len; c0 += RATE) {
     if (live && g < RATE && c0 + g < len) s = elem(c0 + g);
-    s = wide_permute(s, g, grp, xs, rc, circ_rows);
+    s = wide_permute(s, g, rc, circ_rows);
   }
   return s;
 }

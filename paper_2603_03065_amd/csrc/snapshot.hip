@@ -46,14 +46,13 @@ __global__ void __launch_bounds__(WIDE_THREADS)
     k_snap_centroid(const uint64_t *__restrict__ centroids, uint32_t dim, const uint64_t *__restrict__ roots,
                     uint64_t n_list, uint64_t *__restrict__ hashes, const uint64_t *__restrict__ rc,
                     const uint32_t *__restrict__ circ_rows) {
-  __shared__ uint64_t xs[2 * WIDE_THREADS];
   const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
   const uint64_t i = uint64_t(blockIdx.x) * WIDE_PER_BLOCK + grp;
   const bool live = i < n_list;
   const uint64_t *mu = centroids + i * dim;
   const uint64_t *root = roots + i * DIGEST;
   auto elem = [&](uint64_t x) -> uint64_t { return x == 0 ? i : x <= dim ? mu[x - 1] : root[x - 1 - dim]; };
-  const uint64_t s = wide_sponge(1 + uint64_t(dim) + DIGEST, live, elem, g, grp, xs, rc, circ_rows);
+  const uint64_t s = wide_sponge(1 + uint64_t(dim) + DIGEST, live, elem, g, rc, circ_rows);
   if (live && g < DIGEST) hashes[i * DIGEST + g] = gl::canon(s);
 }
 
@@ -61,11 +60,10 @@ __global__ void __launch_bounds__(WIDE_THREADS)
 __global__ void __launch_bounds__(WIDE_THREADS)
     k_snap_codebook(const uint64_t *__restrict__ codebooks, uint64_t len, uint64_t *__restrict__ root_cb,
                     const uint64_t *__restrict__ rc, const uint32_t *__restrict__ circ_rows) {
-  __shared__ uint64_t xs[2 * WIDE_THREADS];
   const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
   const bool live = grp == 0;
   auto elem = [&](uint64_t x) -> uint64_t { return codebooks[x]; };
-  const uint64_t s = wide_sponge(len, live, elem, g, grp, xs, rc, circ_rows);
+  const uint64_t s = wide_sponge(len, live, elem, g, rc, circ_rows);
   if (live && g < DIGEST) root_cb[g] = gl::canon(s);
 }
 
