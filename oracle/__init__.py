@@ -84,6 +84,7 @@ def _load():
         "or_commit": (i32, [pp, _U64P, u32, u32, u32, u64, i32, u32, _U64P, _U64P, _U64P]),
         "or_snapshot_commit": (i32, [pp, u32, u32, u32, u32, u32, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P,
                                      _U64P, _U64P]),
+        "or_grand_product": (i32, [_U64P, u32, u64, u64, u64, _U64P, _U64P]),
         "or_set_threads": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -286,6 +287,22 @@ class Poseidon:
         if rc != 0:
             raise ValueError("oracle commit: invalid arguments")
         return cap, lde_out, tree
+
+
+def grand_product(cols, alpha: int, beta: int, want_z: bool = True):
+    """Running products z_i = prod_{j<=i} (alpha - Compress(row j; beta)) of a column-major
+    table [width][n]; returns (z or None, total)."""
+    c = _u64(cols)
+    if c.ndim == 1:
+        c = c.reshape(1, -1)
+    width, n = c.shape
+    z = np.empty(n, dtype=np.uint64) if want_z else None
+    total = np.zeros(1, dtype=np.uint64)
+    rc = _load().or_grand_product(_ptr(c) if c.size else None, width, n, alpha, beta,
+                                  _ptr(z) if (z is not None and n) else None, _ptr(total))
+    if rc != 0:
+        raise ValueError("oracle grand_product: invalid arguments")
+    return z, int(total[0])
 
 
 def merkle_path(tree: np.ndarray, log_leaves: int, cap_height: int, index: int) -> np.ndarray:

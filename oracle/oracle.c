@@ -495,6 +495,21 @@ int or_snapshot_commit(const or_poseidon_params *pp, uint32_t log_lists, uint32_
   return 0;
 }
 
+int or_grand_product(const uint64_t *cols, uint32_t width, uint64_t n, uint64_t alpha, uint64_t beta,
+                     uint64_t *z, uint64_t *total) {
+  if (width == 0 || !total || (n && !cols)) return -1;
+  uint64_t acc = 1;
+  for (uint64_t i = 0; i < n; i++) {
+    /* Compress by Horner's rule from the last coordinate */
+    uint64_t c = cols[(uint64_t)(width - 1) * n + i];
+    for (int64_t k = (int64_t)width - 2; k >= 0; k--) c = or_add(or_mul(c, beta), cols[(uint64_t)k * n + i]);
+    acc = or_mul(acc, or_sub(alpha, c));
+    if (z) z[i] = acc;
+  }
+  *total = acc;
+  return 0;
+}
+
 int or_set_threads(int n) {
 #ifdef _OPENMP
   if (n > 0) omp_set_num_threads(n);

@@ -153,6 +153,15 @@ int or_snapshot_commit(const or_poseidon_params *pp, uint32_t log_lists, uint32_
                        uint64_t *list_roots, uint64_t *list_hashes, uint64_t root_mk[OR_DIGEST],
                        uint64_t root_cb[OR_DIGEST]);
 
+/* ---- Multiset equality (Sec. 4.5 "Gadgets and Cost Model": tuple compression and SetEq) ----
+ * Rows of a column-major table cols [width][n] (row i = (x_{0,i}, ..., x_{width-1,i})):
+ *   c_i = Compress(row i; beta) = sum_k x_{k,i} beta^k   (Horner)
+ *   z_i = prod_{j <= i} (alpha - c_j)
+ * z [n] is nullable; *total receives z_{n-1} (1 when n = 0). Returns 0, or -1 on
+ * invalid arguments (width = 0). */
+int or_grand_product(const uint64_t *cols, uint32_t width, uint64_t n, uint64_t alpha, uint64_t beta,
+                     uint64_t *z, uint64_t *total);
+
 /* Threads used by the parallel loops (OpenMP); 0 leaves the default. Returns the count in use. */
 int or_set_threads(int n);
 
