@@ -248,6 +248,19 @@ typedef struct {
 v3db_status v3db_snapshot_commit(v3db_ctx *ctx, const v3db_snapshot *snap, uint64_t *d_list_roots,
                                  uint64_t *d_root_mk, uint64_t *d_root_cb, v3db_stream stream);
 
+/* ---------------------------------------------------------------- multiset equality
+ * The grand product behind a multiset-equality check (Sec. 4.5 "Gadgets and Cost
+ * Model": tuple compression with a challenge beta, then SetEq compares
+ * prod (alpha - x_i) of two sequences). For the n rows of a column-major table
+ * d_cols [width][n] (row i = (x_{0,i}, ..., x_{width-1,i}), canonical words):
+ *   c_i = sum_k x_{k,i} beta^k,   z_i = prod_{j <= i} (alpha - c_j)  (mod p).
+ * d_z [n] (nullable) receives the running products, d_total [1] the last one
+ * (1 when n = 0); alpha and beta are reduced mod p. Scratch: 2 words per 4096 rows
+ * from the context. Errors: INVALID_ARG (NULL pointer, width = 0), UNSUPPORTED
+ * (width > 65535 or n >= 2^40), NONCANONICAL (V3DB_VALIDATE=1), DEVICE. */
+v3db_status v3db_grand_product(v3db_ctx *ctx, const uint64_t *d_cols, uint32_t width, uint64_t n, uint64_t alpha,
+                               uint64_t beta, uint64_t *d_z, uint64_t *d_total, v3db_stream stream);
+
 /* ---------------------------------------------------------------- schedules
  * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
  * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):

@@ -182,6 +182,7 @@ def lib():
         "v3db_autotune_lde": (i32, [vp, u32, u32, u32, i32, ctypes.POINTER(_Schedule)]),
         "v3db_open_batch": (i32, [vp, vp, u32, u32, vp, u32, vp, sz, vp, vp, vp]),
         "v3db_snapshot_commit": (i32, [vp, ctypes.POINTER(_Snapshot), vp, vp, vp, vp]),
+        "v3db_grand_product": (i32, [vp, vp, u32, u64, u64, u64, vp, vp, vp]),
         "v3db_verify_batch": (i32, [vp, vp, u32, u32, u32, vp, sz, vp, vp, vp, vp]),
         "v3db_get_schedule": (i32, [vp, u32, u32, ctypes.POINTER(_Schedule)]),
         "v3db_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
@@ -362,6 +363,18 @@ class Context:
         _check(lib().v3db_snapshot_commit(self._h, ctypes.byref(sn), _ptr(list_roots), _ptr(mk), _ptr(cb),
                                           _stream(stream)))
         return mk, cb, list_roots
+
+    def grand_product(self, cols, alpha: int, beta: int, z=None, want_z: bool = True, stream=None):
+        """Running products z_i = prod_{j<=i} (alpha - Compress(row j; beta)) of a column-major
+        table cols [width][n] (int64 device tensor); returns (z or None, total [1])."""
+        import torch
+        width, n = cols.shape
+        if want_z and z is None:
+            z = torch.empty((n,), dtype=torch.int64, device=cols.device)
+        total = torch.empty((1,), dtype=torch.int64, device=cols.device)
+        _check(lib().v3db_grand_product(self._h, _ptr(cols) if n else None, width, n, alpha % P, beta % P,
+                                        _ptr(z) if (want_z and n) else None, _ptr(total), _stream(stream)))
+        return (z if want_z else None), total
 
     @staticmethod
     def _jobs(jobs: Sequence[Job]):

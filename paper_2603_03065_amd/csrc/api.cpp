@@ -581,4 +581,24 @@ v3db_status v3db_snapshot_commit(v3db_ctx *ctx, const v3db_snapshot *sn, uint64_
                           (uint64_t *)z, s);
 }
 
+
+v3db_status v3db_grand_product(v3db_ctx *ctx, const uint64_t *d_cols, uint32_t width, uint64_t n, uint64_t alpha,
+                               uint64_t beta, uint64_t *d_z, uint64_t *d_total, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "grand_product: NULL ctx");
+  if (!d_total || (n && !d_cols)) return set_error(V3DB_ERR_INVALID_ARG, "grand_product: NULL pointer");
+  if (width == 0) return set_error(V3DB_ERR_INVALID_ARG, "grand_product: width must be > 0");
+  if (width > V3DB_MAX_COLS || n >= (uint64_t(1) << 40))
+    return set_error(V3DB_ERR_UNSUPPORTED, "grand_product: width <= 65535 and n < 2^40 required");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  v3db_status st = check_canonical(ctx, d_cols, size_t(width) * n, s);
+  if (st != V3DB_OK) return st;
+  void *z = nullptr;
+  st = ctx_scratch(ctx, s, grand_product_scratch_words(n) * 8, &z);
+  if (st != V3DB_OK) return st;
+  return enqueue_grand_product(ctx, d_cols, width, n, alpha, beta, d_z, d_total, (uint64_t *)z, s);
+}
+
 }  // extern "C"

@@ -145,6 +145,9 @@ void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 // Batched commits (batch.hip). scratch (nullable) replaces the context's
 // per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+size_t grand_product_scratch_words(uint64_t n);
+v3db_status enqueue_grand_product(v3db_ctx *ctx, const uint64_t *cols, uint32_t width, uint64_t n, uint64_t alpha,
+                                  uint64_t beta, uint64_t *z, uint64_t *total, uint64_t *scratch, hipStream_t stream);
 size_t snapshot_scratch_words(uint32_t log_lists, uint32_t log_slots);
 v3db_status enqueue_snapshot(v3db_ctx *ctx, uint32_t log_lists, uint32_t log_slots, uint32_t m, uint32_t dim,
                              uint32_t k, const uint64_t *flag, const uint64_t *item, const uint64_t *codes,

@@ -107,3 +107,9 @@ def test_snapshot_commit_rejects_bad_arguments_without_device(v3db):
     lib = v3db.lib()
     assert lib.v3db_snapshot_commit(None, None, None, None, None, None) == 1
     assert b"NULL ctx" in lib.v3db_last_error()
+
+
+def test_grand_product_rejects_bad_arguments_without_device(v3db):
+    lib = v3db.lib()
+    assert lib.v3db_grand_product(None, None, 1, 4, 1, 2, None, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
