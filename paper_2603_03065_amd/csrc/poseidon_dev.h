@@ -43,6 +43,16 @@ __device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
   return r;
 }
 
+// c + a * x, and acc += a * x, each as one v_mad_u64_u32 (the carry out is unused).
+__device__ __forceinline__ uint64_t mad_start(uint32_t a, uint32_t x, uint64_t c) {
+  uint64_t d;
+  asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=&v"(d) : "v"(a), "v"(x), "s"(c) : "vcc");
+  return d;
+}
+__device__ __forceinline__ void mad_acc(uint64_t &acc, uint32_t a, uint32_t x) {
+  asm("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(acc) : "v"(a), "v"(x) : "vcc");
+}
+
 // state <- M * state + rc_next. The next round's constants enter as the initial
 // values of the two accumulators (their low and high 32-bit halves), so the
 // constant addition costs nothing. All sums stay below 2^44.
@@ -57,12 +67,17 @@ __device__ __forceinline__ void mds_ark(uint64_t s[WIDTH], const uint32_t a[WIDT
 #pragma unroll
   for (int i = 0; i < WIDTH; i++) {
     const uint64_t rc = rc_next[i];
-    uint64_t al = (uint32_t)rc, ah = rc >> 32;
+    // one chain per accumulator with the constant as the first multiply-add's
+    // addend, written as single instructions so the sum is not re-associated into
+    // several chains joined by additions
+    uint64_t al = mad_start(a[(1 - i + WIDTH) % WIDTH], lo[1], (uint32_t)rc);
+    uint64_t ah = mad_start(a[(1 - i + WIDTH) % WIDTH], hi[1], rc >> 32);
 #pragma unroll
-    for (int j = 0; j < WIDTH; j++) {
+    for (int jj = 2; jj <= WIDTH; jj++) {
+      const int j = jj % WIDTH;  // word 0 (a partial round's only S-box output) last
       const uint32_t c = a[(j - i + WIDTH) % WIDTH];
-      al += (uint64_t)c * lo[j];
-      ah += (uint64_t)c * hi[j];
+      mad_acc(al, c, lo[j]);
+      mad_acc(ah, c, hi[j]);
     }
     s[i] = fold(al, ah);
   }
@@ -87,7 +102,7 @@ __device__ __forceinline__ void permute(uint64_t s[WIDTH], const uint64_t *__res
     for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
     mds_ark(s, a, rc + (r + 1) * WIDTH);
   }
-#pragma unroll 1
+#pragma unroll 2
   for (int r = FULL_HALF; r < ROUNDS - FULL_HALF; r++) {
     s[0] = sbox(s[0]);
     mds_ark(s, a, rc + (r + 1) * WIDTH);
