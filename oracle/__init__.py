@@ -85,6 +85,7 @@ def _load():
         "or_snapshot_commit": (i32, [pp, u32, u32, u32, u32, u32, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P, _U64P,
                                      _U64P, _U64P]),
         "or_grand_product": (i32, [_U64P, u32, u64, u64, u64, _U64P, _U64P]),
+        "or_fri_commit": (i32, [pp, _U64P, u32, u64, _U64P, u32, u32, _U64P, _U64P, _U64P]),
         "or_set_threads": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -244,6 +245,25 @@ class Poseidon:
         if rc != 0:
             raise ValueError("oracle snapshot_commit: invalid arguments")
         return mk, cb, roots, hashes
+
+    def fri_commit(self, codeword, shift: int, betas, cap_height: int, want_trees: bool = False):
+        """FRI commit phase over a codeword of 2^L values on the coset shift * <w_{2^L}>: per round
+        the pair-leaf tree's cap, then the fold with betas[r]. Returns (folded f_1..f_R
+        concatenated, caps [R][2^h][4], trees concatenated or None)."""
+        f = _u64(codeword)
+        n = f.size
+        log_n = n.bit_length() - 1
+        b = _u64(betas)
+        rounds = b.size
+        folded = np.empty(n - (n >> rounds), dtype=np.uint64)
+        caps = np.empty((rounds, 1 << cap_height, DIGEST), dtype=np.uint64)
+        words = sum(((n >> r) - (1 << cap_height)) * DIGEST for r in range(rounds))
+        trees = np.empty(words, dtype=np.uint64) if want_trees else None
+        rc = _load().or_fri_commit(ctypes.byref(self._p), _ptr(f), log_n, shift, _ptr(b), rounds, cap_height,
+                                   _ptr(folded), _ptr(trees) if trees is not None else None, _ptr(caps))
+        if rc != 0:
+            raise ValueError("oracle fri_commit: invalid arguments")
+        return folded, caps, trees
 
     def leaf_digests(self, mat: np.ndarray) -> np.ndarray:
         m = _u64(mat)

@@ -510,6 +510,44 @@ int or_grand_product(const uint64_t *cols, uint32_t width, uint64_t n, uint64_t 
   return 0;
 }
 
+int or_fri_commit(const or_poseidon_params *pp, const uint64_t *codeword, uint32_t log_n, uint64_t shift,
+                  const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *folded, uint64_t *trees,
+                  uint64_t *caps) {
+  if (!pp || !codeword || !folded || !caps || (rounds && !betas)) return -1;
+  if (rounds == 0 || rounds > log_n || cap_height + rounds > log_n || shift % OR_P == 0) return -1;
+  const uint64_t inv2 = or_inv(2);
+  const uint64_t *f = codeword;
+  uint64_t *next = folded, *tree_out = trees;
+  uint64_t s_r = shift % OR_P;
+  for (uint32_t r = 0; r < rounds; r++) {
+    const uint32_t log_nr = log_n - r;
+    const uint64_t nr = 1ULL << log_nr, half = nr / 2;
+    /* commit: leaves are the pairs (f[k], f[k + N/2]); a matrix [2][N/2] hashed by rows */
+    const uint64_t tree_words = (2 * half - (1ULL << cap_height)) * OR_DIGEST;
+    uint64_t *t = tree_out ? tree_out : (uint64_t *)malloc(sizeof(uint64_t) * tree_words);
+    if (!t) return -1;
+    int rc = or_merkle_commit(pp, f, 2, log_nr - 1, cap_height, t, caps + (uint64_t)r * (OR_DIGEST << cap_height));
+    if (!tree_out) free(t);
+    if (rc != 0) return -1;
+    if (tree_out) tree_out += tree_words;
+    /* fold with beta_r */
+    const uint64_t w = or_root_of_unity(log_nr), winv = or_inv(w), sinv = or_inv(s_r);
+    const uint64_t beta = betas[r] % OR_P;
+    uint64_t xinv = sinv; /* 1 / x_k for k = 0, then times w^-1 */
+    for (uint64_t k = 0; k < half; k++) {
+      const uint64_t a = f[k], b = f[k + half];
+      const uint64_t even = or_mul(or_add(a, b), inv2);
+      const uint64_t odd = or_mul(or_mul(or_sub(a, b), inv2), xinv);
+      next[k] = or_add(even, or_mul(beta, odd));
+      xinv = or_mul(xinv, winv);
+    }
+    f = next;
+    next += half;
+    s_r = or_mul(s_r, s_r);
+  }
+  return 0;
+}
+
 int or_set_threads(int n) {
 #ifdef _OPENMP
   if (n > 0) omp_set_num_threads(n);

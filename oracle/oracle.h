@@ -162,6 +162,22 @@ int or_snapshot_commit(const or_poseidon_params *pp, uint32_t log_lists, uint32_
 int or_grand_product(const uint64_t *cols, uint32_t width, uint64_t n, uint64_t alpha, uint64_t beta,
                      uint64_t *z, uint64_t *total);
 
+/* ---- FRI commit phase: the low-degree test of the paper's proving backend, which
+ * Sec. 5 para. "Evaluation environment" runs with its default FRI parameters; the
+ * arity-2 folding and pair-leaf commitment below are the standard commit phase ----
+ * Round r = 0..rounds-1 holds the codeword f_r of length N_r = 2^(log_n - r) on the
+ * coset D_r = { s_r w_{N_r}^k }, s_0 = shift, s_{r+1} = s_r^2, natural order.
+ *   commit:  leaf k < N_r/2 = Hash(f_r[k], f_r[k + N_r/2]) (the two points x, -x of D_r);
+ *            a Merkle tree of those N_r/2 leaves up to cap_height; caps [rounds][2^h][4]
+ *   fold:    f_{r+1}[k] = (f_r[k] + f_r[k + N_r/2]) / 2
+ *                         + beta_r (f_r[k] - f_r[k + N_r/2]) / (2 x_k),   x_k = s_r w_{N_r}^k
+ * folded receives f_1, ..., f_rounds concatenated (2^log_n - 2^(log_n - rounds) words);
+ * trees (nullable) the rounds' trees concatenated, each [N_r - 2^h][4].
+ * Returns 0, or -1 on invalid arguments (rounds = 0, rounds + cap_height > log_n, shift = 0 mod p). */
+int or_fri_commit(const or_poseidon_params *pp, const uint64_t *codeword, uint32_t log_n, uint64_t shift,
+                  const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *folded, uint64_t *trees,
+                  uint64_t *caps);
+
 /* Threads used by the parallel loops (OpenMP); 0 leaves the default. Returns the count in use. */
 int or_set_threads(int n);
 
