@@ -38,9 +38,8 @@ __device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
   const uint64_t t = (uint64_t)(uint32_t)(hi >> 32) * gl::EPS + lo;
   const uint32_t th = (uint32_t)(t >> 32);
   const uint32_t rh = th + (uint32_t)hi;
-  uint64_t r = ((uint64_t)rh << 32) | (uint32_t)t;
-  if (rh < th) r += gl::EPS;
-  return r;
+  const uint64_t r = ((uint64_t)rh << 32) | (uint32_t)t;
+  return r + (rh < th ? gl::EPS : 0);
 }
 
 // c + a * x, and acc += a * x, each as one v_mad_u64_u32 (the carry out is unused).
