@@ -37,6 +37,7 @@ WORKLOADS = {
 }
 BATCH_WORKLOAD = "commit-batch-64"   # 64 traces: log rows U{10..18}, cols U[20,135], blowup 8, cap 2
 OPEN_WORKLOAD = "open-8192"          # 8192 openings (rows + paths) of the 80 x 2^18 commitment, and their check
+FRI_WORKLOAD = "fri-2^23"            # FRI commit phase over a 2^23-point codeword: 17 rounds, cap height 4
 MULTISET_WORKLOAD = "multiset-2^24"  # running products of alpha - Compress(row; beta) over 2^24 rows of 4-tuples
 SNAPSHOT_WORKLOADS = {
     # name: (description, log_lists, log_slots, M, D, K, data seed)
@@ -84,7 +85,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
-                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, "serve-poisson", OPEN_WORKLOAD, MULTISET_WORKLOAD]
+                    choices=sorted(WORKLOADS) + [BATCH_WORKLOAD, "serve-poisson", OPEN_WORKLOAD, MULTISET_WORKLOAD, FRI_WORKLOAD]
                     + sorted(SNAPSHOT_WORKLOADS))
     ap.add_argument("--serve-seconds", type=float, default=120.0)
     ap.add_argument("--serve-rate", type=float, default=50.0)
@@ -318,6 +319,61 @@ def snapshot_main(args):
     print(json.dumps(out), flush=True)
 
 
+def fri_main(args):
+    """FRI commit phase over a 2^23-point codeword (the extension size of a
+    135 x 2^20 trace at blowup 8) resident in HBM: 17 rounds of pair-leaf tree, cap
+    (height 4) and arity-2 fold, down to a 64-point codeword."""
+    import numpy as np
+    import torch
+
+    import paper_2603_03065_amd as v3db
+    from paper_2603_03065_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log_n, rounds, h = 23, 17, 4
+    n = 1 << log_n
+    f0 = v3db.to_device(inputs.canon(inputs.splitmix64(130, np.arange(n, dtype=np.uint64))), dev)
+    betas = [int(b) % inputs.P for b in inputs.splitmix64(131, np.arange(rounds, dtype=np.uint64))]
+    ctx = v3db.Context(0)
+    stream = torch.cuda.current_stream(dev)
+    folded = torch.empty((n - (n >> rounds),), dtype=torch.int64, device=dev)
+    caps = torch.empty((rounds, 1 << h, 4), dtype=torch.int64, device=dev)
+    words = sum(((n >> r) - (1 << h)) * 4 for r in range(rounds))
+    trees = torch.empty((words,), dtype=torch.int64, device=dev)
+    call = lambda: ctx.fri_commit(f0, 7, betas, h, folded, trees, caps, stream=stream)
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        call()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    perms = sum((n >> r) - (1 << h) for r in range(rounds))   # leaves + compressions of every round
+    out = {
+        "metric": "FRI commit-phase codeword points per second at 1 GPU",
+        "value": n * args.steps / wall,
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{FRI_WORKLOAD}: 2^23-point codeword on the coset 7<w>, {rounds} rounds (pair-leaf "
+                               f"tree, cap height {h}, arity-2 fold) to a {n >> rounds}-point codeword",
+                   "points": n, "rounds": rounds, "cap_height": h},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "permutations_per_step": perms,
+        "permutations_per_s": perms / (float(step_ms.mean()) / 1e3),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def multiset_main(args):
     """Grand product of a multiset-equality check over 2^24 rows of 4-element tuples
     resident in HBM: per step the compressed factors alpha - sum x_k beta^k and all
@@ -514,6 +570,8 @@ def main():
         return snapshot_main(args)
     if args.workload == MULTISET_WORKLOAD:
         return multiset_main(args)
+    if args.workload == FRI_WORKLOAD:
+        return fri_main(args)
 
     import numpy as np
     import torch

@@ -261,6 +261,26 @@ v3db_status v3db_snapshot_commit(v3db_ctx *ctx, const v3db_snapshot *snap, uint6
 v3db_status v3db_grand_product(v3db_ctx *ctx, const uint64_t *d_cols, uint32_t width, uint64_t n, uint64_t alpha,
                                uint64_t beta, uint64_t *d_z, uint64_t *d_total, v3db_stream stream);
 
+/* ---------------------------------------------------------------- FRI commit phase
+ * The low-degree test of the proving backend (Sec. 5 para. "Evaluation environment":
+ * the backend's default FRI parameters), commit phase with arity 2. Round
+ * r = 0..rounds-1 holds the codeword f_r of N_r = 2^(log_n - r) values on the coset
+ * { s_r w_{N_r}^k } (s_0 = shift, s_{r+1} = s_r^2, natural order; f_0 = d_codeword):
+ *   commit:  leaf k < N_r/2 = Hash(f_r[k], f_r[k + N_r/2]) (the points x and -x), a
+ *            Merkle tree of those leaves up to cap_height, cap r -> d_caps[r]
+ *   fold:    f_{r+1}[k] = (f_r[k] + f_r[k + N_r/2])/2 + beta_r (f_r[k] - f_r[k + N_r/2])/(2 x_k)
+ * betas: host array [rounds], the challenges (reduced mod p).
+ * d_folded: device [2^log_n - 2^(log_n - rounds)] receives f_1 .. f_rounds concatenated.
+ * d_trees:  device, nullable, receives the rounds' trees concatenated (round r:
+ *           [N_r - 2^cap_height][4], leaves first); when NULL a context scratch tree
+ *           is used per round. d_caps: device [rounds][2^cap_height][4].
+ * Errors: INVALID_ARG (NULL pointer, rounds = 0, rounds + cap_height > log_n,
+ * shift = 0 mod p), UNSUPPORTED (log_n > 26), NONCANONICAL (V3DB_VALIDATE=1),
+ * OUT_OF_MEMORY, DEVICE. */
+v3db_status v3db_fri_commit(v3db_ctx *ctx, const uint64_t *d_codeword, uint32_t log_n, uint64_t shift,
+                            const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *d_folded,
+                            uint64_t *d_trees, uint64_t *d_caps, v3db_stream stream);
+
 /* ---------------------------------------------------------------- schedules
  * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
  * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):

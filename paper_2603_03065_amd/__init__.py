@@ -183,6 +183,7 @@ def lib():
         "v3db_open_batch": (i32, [vp, vp, u32, u32, vp, u32, vp, sz, vp, vp, vp]),
         "v3db_snapshot_commit": (i32, [vp, ctypes.POINTER(_Snapshot), vp, vp, vp, vp]),
         "v3db_grand_product": (i32, [vp, vp, u32, u64, u64, u64, vp, vp, vp]),
+        "v3db_fri_commit": (i32, [vp, vp, u32, u64, vp, u32, u32, vp, vp, vp, vp]),
         "v3db_verify_batch": (i32, [vp, vp, u32, u32, u32, vp, sz, vp, vp, vp, vp]),
         "v3db_get_schedule": (i32, [vp, u32, u32, ctypes.POINTER(_Schedule)]),
         "v3db_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
@@ -375,6 +376,28 @@ class Context:
         _check(lib().v3db_grand_product(self._h, _ptr(cols) if n else None, width, n, alpha % P, beta % P,
                                         _ptr(z) if (want_z and n) else None, _ptr(total), _stream(stream)))
         return (z if want_z else None), total
+
+    def fri_commit(self, codeword, shift: int, betas, cap_height: int, folded=None, trees=None, caps=None,
+                   want_trees: bool = False, stream=None):
+        """FRI commit phase over a codeword (int64 device tensor of 2^L values on the coset shift *
+        <w_{2^L}>), one round per challenge in betas. Returns (folded f_1..f_R concatenated,
+        caps [R][2^h][4], trees concatenated or None)."""
+        import torch
+        n = codeword.numel()
+        log_n = n.bit_length() - 1
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.uint64))
+        rounds = b.size
+        dev = codeword.device
+        if folded is None:
+            folded = torch.empty((n - (n >> rounds),), dtype=torch.int64, device=dev)
+        if caps is None:
+            caps = torch.empty((rounds, 1 << cap_height, 4), dtype=torch.int64, device=dev)
+        if want_trees and trees is None:
+            words = sum(((n >> r) - (1 << cap_height)) * 4 for r in range(rounds))
+            trees = torch.empty((words,), dtype=torch.int64, device=dev)
+        _check(lib().v3db_fri_commit(self._h, _ptr(codeword), log_n, shift, b.ctypes.data, rounds, cap_height,
+                                     _ptr(folded), _ptr(trees), _ptr(caps), _stream(stream)))
+        return folded, caps, trees
 
     @staticmethod
     def _jobs(jobs: Sequence[Job]):

@@ -601,4 +601,29 @@ v3db_status v3db_grand_product(v3db_ctx *ctx, const uint64_t *d_cols, uint32_t w
   return enqueue_grand_product(ctx, d_cols, width, n, alpha, beta, d_z, d_total, (uint64_t *)z, s);
 }
 
+
+v3db_status v3db_fri_commit(v3db_ctx *ctx, const uint64_t *d_codeword, uint32_t log_n, uint64_t shift,
+                            const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *d_folded,
+                            uint64_t *d_trees, uint64_t *d_caps, v3db_stream stream) {
+  clear_error();
+  if (!ctx) return set_error(V3DB_ERR_INVALID_ARG, "fri_commit: NULL ctx");
+  if (!d_codeword || !betas || !d_folded || !d_caps) return set_error(V3DB_ERR_INVALID_ARG, "fri_commit: NULL pointer");
+  if (log_n > V3DB_MAX_LOG_LDE) return set_error(V3DB_ERR_UNSUPPORTED, "fri_commit: log_n > 26");
+  if (rounds == 0 || rounds + cap_height > log_n)
+    return set_error(V3DB_ERR_INVALID_ARG, "fri_commit: need 1 <= rounds and rounds + cap_height <= log_n");
+  if (shift % gl::P == 0) return set_error(V3DB_ERR_INVALID_ARG, "fri_commit: shift is 0 mod p");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  v3db_status st = check_canonical(ctx, d_codeword, size_t(1) << log_n, s);
+  if (st != V3DB_OK) return st;
+  void *z = nullptr;
+  if (!d_trees) {
+    st = ctx_scratch(ctx, s, ((size_t(1) << log_n) - (size_t(1) << cap_height)) * DIGEST * 8, &z);
+    if (st != V3DB_OK) return st;
+  }
+  return enqueue_fri_commit(ctx, d_codeword, log_n, shift, betas, rounds, cap_height, d_folded, d_trees, d_caps,
+                            (uint64_t *)z, s);
+}
+
 }  // extern "C"

@@ -145,6 +145,10 @@ void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 // Batched commits (batch.hip). scratch (nullable) replaces the context's
 // per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+size_t fri_tree_digests(uint32_t log_n, uint32_t rounds, uint32_t cap_height);
+v3db_status enqueue_fri_commit(v3db_ctx *ctx, const uint64_t *codeword, uint32_t log_n, uint64_t shift,
+                               const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *folded,
+                               uint64_t *trees, uint64_t *caps, uint64_t *scratch_tree, hipStream_t stream);
 size_t grand_product_scratch_words(uint64_t n);
 v3db_status enqueue_grand_product(v3db_ctx *ctx, const uint64_t *cols, uint32_t width, uint64_t n, uint64_t alpha,
                                   uint64_t beta, uint64_t *z, uint64_t *total, uint64_t *scratch, hipStream_t stream);

@@ -113,3 +113,9 @@ def test_grand_product_rejects_bad_arguments_without_device(v3db):
     lib = v3db.lib()
     assert lib.v3db_grand_product(None, None, 1, 4, 1, 2, None, None, None) == 1
     assert b"NULL ctx" in lib.v3db_last_error()
+
+
+def test_fri_commit_rejects_bad_arguments_without_device(v3db):
+    lib = v3db.lib()
+    assert lib.v3db_fri_commit(None, None, 4, 7, None, 1, 0, None, None, None, None) == 1
+    assert b"NULL ctx" in lib.v3db_last_error()
