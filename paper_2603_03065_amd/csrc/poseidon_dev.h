@@ -186,7 +186,17 @@ __device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, const uint64
     const uint64_t rc_next = rcn;
     if (r + 1 < ROUNDS) rcn = rc[(r + 2) * WIDTH + gi];
     const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
-    if (full || g == 0) s = sbox(s);
+    if (full) {
+      s = sbox(s);
+    } else {
+      // x^7 of word 0 with two lanes: every lane forms x^2, lane 1 then x^4 while the
+      // others form x^3, and x^3 * x^4 (three dependent products instead of four)
+      const uint64_t x = row_bcast<0>(s);
+      const uint64_t x2 = gl::mul_r(x, x);
+      const uint64_t y = gl::mul_r(x2, g == 1 ? x2 : x);
+      const uint64_t x7 = gl::mul_r(y, row_bcast<1>(y));
+      if (g == 0) s = x7;
+    }
     uint64_t al = (uint32_t)rc_next, ah = rc_next >> 32;
     mds_term<0>(s, m, al, ah);
     mds_term<1>(s, m, al, ah);
