@@ -369,6 +369,14 @@ def fri_main(args):
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "permutations_per_step": perms,
         "permutations_per_s": perms / (float(step_ms.mean()) / 1e3),
+        # the trees (one permutation per leaf pair and per inner node) are the work; the
+        # folds read 16 and write 8 bytes per output point, about 0.4 ms at HBM speed
+        "roofline": {"kernel": "k_leaf_hash + k_merkle_level(_wide) of every round, on side streams", "bound": "alu",
+                     "achieved": perms * OPS_PER_PERMUTATION / (float(step_ms.mean()) / 1e3) / 1e12,
+                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU lane-ops)",
+                     "frac": perms * OPS_PER_PERMUTATION / (float(step_ms.mean()) / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                     "traffic": None, "ops_per_step": perms * OPS_PER_PERMUTATION,
+                     "timed_over": "the whole step (trees overlap the fold chain)"},
     }
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -95,6 +95,11 @@ struct v3db_ctx {
   hipStream_t capture_stream = nullptr;
   hipStream_t side_stream = nullptr;  // snapshot codebook digest, forked from and joined into the caller's stream
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // FRI: round trees on side streams, overlapping the fold chain on the caller's stream
+  static constexpr int FRI_STREAMS = 4;
+  hipStream_t fri_streams[FRI_STREAMS] = {};
+  hipEvent_t fri_done[FRI_STREAMS] = {};
+  hipEvent_t fri_ready[V3DB_MAX_LOG_LDE + 1] = {};
   std::mutex mu;
 };
 

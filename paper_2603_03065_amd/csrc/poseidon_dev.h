@@ -22,11 +22,14 @@ struct Circ {
   uint32_t a[WIDTH];
 };
 
+// x^7; LAT selects the multiplication with the shorter dependent chain
+template <bool LAT = false>
 __device__ __forceinline__ uint64_t sbox(uint64_t x) {
-  const uint64_t x2 = gl::mul_r(x, x);
-  const uint64_t x3 = gl::mul_r(x2, x);
-  const uint64_t x4 = gl::mul_r(x2, x2);
-  return gl::mul_r(x3, x4);
+  auto mul = [](uint64_t a, uint64_t b) { return LAT ? gl::mul_r_lat(a, b) : gl::mul_r(a, b); };
+  const uint64_t x2 = mul(x, x);
+  const uint64_t x3 = mul(x2, x);
+  const uint64_t x4 = mul(x2, x2);
+  return mul(x3, x4);
 }
 
 // lo + hi * 2^32 for lo, hi < 2^46, to a relaxed value: with hi = hh*2^32 + hl,
@@ -187,14 +190,14 @@ __device__ __forceinline__ uint64_t wide_permute(uint64_t s, int g, const uint64
     if (r + 1 < ROUNDS) rcn = rc[(r + 2) * WIDTH + gi];
     const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
     if (full) {
-      s = sbox(s);
+      s = sbox<true>(s);
     } else {
       // x^7 of word 0 with two lanes: every lane forms x^2, lane 1 then x^4 while the
       // others form x^3, and x^3 * x^4 (three dependent products instead of four)
       const uint64_t x = row_bcast<0>(s);
-      const uint64_t x2 = gl::mul_r(x, x);
-      const uint64_t y = gl::mul_r(x2, g == 1 ? x2 : x);
-      const uint64_t x7 = gl::mul_r(y, row_bcast<1>(y));
+      const uint64_t x2 = gl::mul_r_lat(x, x);
+      const uint64_t y = gl::mul_r_lat(x2, g == 1 ? x2 : x);
+      const uint64_t x7 = gl::mul_r_lat(y, row_bcast<1>(y));
       if (g == 0) s = x7;
     }
     uint64_t al = (uint32_t)rc_next, ah = rc_next >> 32;
