@@ -57,7 +57,36 @@ HBM_PEAK_GBS = 8000.0
 #   = 16,600 32-bit integer operations;
 #   one LDE element = 9 bytes of HBM traffic (1/8 element read, 1 element written).
 OPS_PER_PERMUTATION = 472 * 10 + 4320 * 2 + 360 * 3 + 360 * 6
+#   With the linear layer on the int8 matrix cores (the default), the VALU's share of
+#   that model is the S-boxes, constants and folds, 472 x 10 + 360 x 3 + 360 x 6 = 7,960
+#   operations, and the matrix cores' is the 144 products of a small entry by a
+#   64-bit word per round as 8 byte products each: 30 x 144 x 8 = 34,560 int8
+#   multiply-adds = 69,120 int8 operations per permutation.
+VALU_OPS_PER_PERMUTATION_MF = 472 * 10 + 360 * 3 + 360 * 6
+INT8_OPS_PER_PERMUTATION_MF = 30 * 144 * 8 * 2
+INT8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of one MI355X
 LDE_BYTES_PER_ELEMENT = 9
+
+
+def hash_roofline(kernel: str, perms: int, seconds: float, path: str, workload: str, extra=None):
+    """Roofline object of a bulk hashing kernel: the VALU's algorithmic operations
+    against the 32-bit VALU peak; with the matrix-core linear layer also its int8 work
+    against the int8 peak, and the whole model counted as VALU operations (the figure
+    the VALU form is measured by) for comparison."""
+    valu_ops = VALU_OPS_PER_PERMUTATION_MF if path == "mfma" else OPS_PER_PERMUTATION
+    achieved = perms * valu_ops / seconds / 1e12
+    r = {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+         "unit": "Tops/s (32-bit integer VALU lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
+         "traffic": measured_traffic(kernel, workload), "linear_layer": path, "ops_per_launch": perms * valu_ops}
+    if path == "mfma":
+        i8 = perms * INT8_OPS_PER_PERMUTATION_MF / seconds / 1e12
+        r["matrix_cores"] = {"achieved": i8, "peak": INT8_PEAK_TOPS, "unit": "int8 TOPS", "frac": i8 / INT8_PEAK_TOPS,
+                             "ops_per_launch": perms * INT8_OPS_PER_PERMUTATION_MF}
+        r["whole_model_as_valu_ops"] = {"ops_per_launch": perms * OPS_PER_PERMUTATION,
+                                        "achieved": perms * OPS_PER_PERMUTATION / seconds / 1e12}
+    if extra:
+        r.update(extra)
+    return r
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -371,12 +400,9 @@ def fri_main(args):
         "permutations_per_s": perms / (float(step_ms.mean()) / 1e3),
         # the trees (one permutation per leaf pair and per inner node) are the work; the
         # folds read 16 and write 8 bytes per output point, about 0.4 ms at HBM speed
-        "roofline": {"kernel": "k_leaf_hash + k_merkle_level(_wide) of every round, on side streams", "bound": "alu",
-                     "achieved": perms * OPS_PER_PERMUTATION / (float(step_ms.mean()) / 1e3) / 1e12,
-                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU lane-ops)",
-                     "frac": perms * OPS_PER_PERMUTATION / (float(step_ms.mean()) / 1e3) / 1e12 / VALU_PEAK_TOPS,
-                     "traffic": None, "ops_per_step": perms * OPS_PER_PERMUTATION,
-                     "timed_over": "the whole step (trees overlap the fold chain)"},
+        "roofline": hash_roofline("leaf and tree kernels of every round, on side streams", perms,
+                                  float(step_ms.mean()) / 1e3, ctx.hash_path, args.workload,
+                                  {"timed_over": "the whole step (trees overlap the fold chain)"}),
     }
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -628,7 +654,6 @@ def main():
     mk_ms, mk_n = phases["merkle"]
     perms_leaf = N * math.ceil(C / 8)
     leaf_avg_s = leaf_ms / max(leaf_n, 1) / 1e3
-    achieved = perms_leaf * OPS_PER_PERMUTATION / leaf_avg_s / 1e12
     lde_avg_s = lde_ms / max(lde_n, 1) / 1e3
     lde_gbs = elems * LDE_BYTES_PER_ELEMENT / lde_avg_s / 1e9
     mk_avg_s = mk_ms / max(mk_n, 1) / 1e3
@@ -659,18 +684,10 @@ def main():
         "trace_elements_per_s": C * n * args.steps / wall,
         "lde_schedule": {"used": schedule, "default": default_schedule,
                          "autotuned": not args.no_autotune},
-        "roofline": {
-            "kernel": "k_leaf_hash (rate-8 Poseidon sponge over every extended row)",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "Tops/s (32-bit integer VALU lane-ops)",
-            "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": measured_traffic("k_leaf_hash", args.workload),
-            "algorithmic_bytes": elems * 8 + N * 32,
-            "ops_per_launch": perms_leaf * OPS_PER_PERMUTATION,
-            "avg_launch_ms": leaf_avg_s * 1e3,
-        },
+        "roofline": hash_roofline("k_leaf_hash_mf" if ctx.hash_path == "mfma" else "k_leaf_hash", perms_leaf,
+                                  leaf_avg_s, ctx.hash_path, args.workload,
+                                  {"algorithmic_bytes": elems * 8 + N * 32, "avg_launch_ms": leaf_avg_s * 1e3,
+                                   "what": "rate-8 Poseidon sponge over every extended row"}),
         "phases": {
             "lde": {"avg_ms": lde_avg_s * 1e3, "bound": "hbm", "achieved_GBps": lde_gbs, "peak_GBps": HBM_PEAK_GBS,
                     "frac": lde_gbs / HBM_PEAK_GBS, "algorithmic_bytes": elems * LDE_BYTES_PER_ELEMENT},

@@ -92,6 +92,19 @@ const char *v3db_last_error(void);
 v3db_status v3db_poseidon_constants(const v3db_ctx *ctx, uint64_t *rc_out, uint64_t *circ_out,
                                     uint32_t *attempts_out);
 
+/* Which form the context's bulk hashing kernels (leaf rows, tree levels of more
+ * than 2^15 nodes, batch phases, snapshot records) use for the permutation's
+ * linear layer (the circulant product of the hash fixed above); both give
+ * identical results, the arithmetic being exact.
+ *   1  int8 matrix cores: every circulant entry is at most 254, so each splits
+ *      into two signed bytes (the default seed's entries are all below 230);
+ *   0  VALU multiply-adds: an entry equals 255, or the environment variable
+ *      V3DB_POSEIDON_VALU was set to a non-zero value when the context was made;
+ *  -1  ctx is NULL.
+ * The single-permutation call, openings, tree tops and the FRI fold are the same
+ * either way. */
+int v3db_ctx_hash_path(const v3db_ctx *ctx);
+
 /* Host only (no device, no context): the constants a context created with
  * `poseidon_seed` uses, as in v3db_poseidon_constants. Takes about a second the
  * first time per seed in a process (the exhaustive submatrix check). Returns

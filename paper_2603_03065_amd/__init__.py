@@ -163,6 +163,7 @@ def lib():
         "v3db_ctx_destroy": (None, [vp]),
         "v3db_last_error": (ctypes.c_char_p, []),
         "v3db_poseidon_constants": (i32, [vp, vp, vp, ctypes.POINTER(u32)]),
+        "v3db_ctx_hash_path": (i32, [vp]),
         "v3db_derive_poseidon_constants": (i32, [u64, vp, vp, ctypes.POINTER(u32)]),
         "v3db_lde": (i32, [vp, vp, u32, u32, u32, u64, i32, vp, vp]),
         "v3db_poseidon_permute": (i32, [vp, vp, sz, vp]),
@@ -283,6 +284,12 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def hash_path(self) -> str:
+        """'mfma' (int8 matrix cores) or 'valu': the form of the permutation's linear
+        layer the bulk hashing kernels of this context use (results are identical)."""
+        return {1: "mfma", 0: "valu"}[lib().v3db_ctx_hash_path(self._h)]
 
     def poseidon_constants(self):
         rc = np.zeros((30, 12), dtype=np.uint64)

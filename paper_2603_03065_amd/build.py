@@ -20,6 +20,9 @@ COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in VGPRs: the hash kernels consume them with VALU multiply-adds
+    # at once, and reading them back from AGPRs would cost one move per word
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",
 ]
 

@@ -229,6 +229,20 @@ v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budge
   if (st == V3DB_OK)
     st = hip_check(hipMemcpy(ctx->d_pos, table, sizeof(table), hipMemcpyHostToDevice), "upload Poseidon constants");
   if (st == V3DB_OK) ctx->d_circ_rows = reinterpret_cast<const uint32_t *>(ctx->d_pos + (ROUNDS + 1) * WIDTH);
+  // the matrix-core linear layer, when the circulant's entries allow it (V3DB_POSEIDON_VALU=1
+  // keeps the VALU form regardless)
+  if (st == V3DB_OK) {
+    std::vector<uint64_t> mf(MF_TABLE_WORDS);
+    const char *env = getenv("V3DB_POSEIDON_VALU");
+    const bool force_valu = env && env[0] && strcmp(env, "0") != 0;
+    if (build_mf_table(ctx->pos, mf.data()) && !force_valu) {
+      st = ctx_alloc(ctx, (void **)&ctx->d_mf, MF_TABLE_WORDS * 8, "Poseidon matrix-core table");
+      if (st == V3DB_OK)
+        st = hip_check(hipMemcpy(ctx->d_mf, mf.data(), MF_TABLE_WORDS * 8, hipMemcpyHostToDevice),
+                       "upload Poseidon matrix-core table");
+      ctx->mf = st == V3DB_OK;
+    }
+  }
   if (st == V3DB_OK) st = build_twiddles(ctx);
   if (st != V3DB_OK) {
     v3db_ctx_destroy(ctx);
@@ -259,6 +273,7 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   ctx->scratch.clear();
   free_twiddles(ctx);
   ctx_free(ctx, ctx->d_pos, POS_TABLE_WORDS * 8);
+  if (ctx->d_mf) ctx_free(ctx, ctx->d_mf, MF_TABLE_WORDS * 8);
   delete ctx;
 }
 
@@ -320,6 +335,8 @@ v3db_status v3db_set_option(v3db_ctx *ctx, v3db_option opt, uint64_t value) {
   }
   return set_error(V3DB_ERR_INVALID_ARG, "set_option: unknown option");
 }
+
+int v3db_ctx_hash_path(const v3db_ctx *ctx) { return ctx ? (ctx->mf ? 1 : 0) : -1; }
 
 v3db_status v3db_derive_poseidon_constants(uint64_t poseidon_seed, uint64_t *rc_out, uint64_t *circ_out,
                                            uint32_t *attempts_out) {

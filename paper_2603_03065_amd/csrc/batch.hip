@@ -17,7 +17,7 @@
 #include <string>
 
 #include "lde_dev.h"
-#include "poseidon_dev.h"
+#include "poseidon_mf.h"
 
 namespace v3db {
 
@@ -89,6 +89,21 @@ __global__ void __launch_bounds__(POS_THREADS) k_batch_leaf(const BJob *__restri
   }
 }
 
+// The same with the matrix-core linear layer: each wave covers 64 consecutive rows.
+__global__ void __launch_bounds__(POS_THREADS) k_batch_leaf_mf(const BJob *__restrict__ jobs,
+                                                                const BRange *__restrict__ ranges, int n_ranges,
+                                                                const uint64_t *__restrict__ rc,
+                                                                const uint64_t *__restrict__ tab) {
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint64_t n_rows = uint64_t(1) << j.logN;
+  const uint64_t base = uint64_t(blockIdx.x - r.first) * LEAF_ROWS + (threadIdx.x & ~63u);
+  if (base >= n_rows) return;  // whole waves only
+  const pos::MfLane L = pos::mf_lane(tab);
+  pos::leaf_digests_mf(j.t.lde, j.n_cols, n_rows, base, j.tree, L, rc, tab,
+                       j.cap_height == j.logN ? j.cap : nullptr);
+}
+
 // Tree depth `depth` (1 = the level above the leaves) of every listed job.
 __global__ void __launch_bounds__(POS_THREADS) k_batch_merkle(const BJob *__restrict__ jobs,
                                                                const BRange *__restrict__ ranges, int n_ranges,
@@ -111,6 +126,23 @@ __global__ void __launch_bounds__(POS_THREADS) k_batch_merkle(const BJob *__rest
 #pragma unroll
     for (int i = 0; i < DIGEST; i++) j.cap[k * DIGEST + i] = d[i];
   }
+}
+
+__global__ void __launch_bounds__(POS_THREADS) k_batch_merkle_mf(const BJob *__restrict__ jobs,
+                                                                  const BRange *__restrict__ ranges, int n_ranges,
+                                                                  int depth, const uint64_t *__restrict__ rc,
+                                                                  const uint64_t *__restrict__ tab) {
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint32_t level = j.logN - depth;
+  const uint64_t count = uint64_t(1) << level;
+  const uint64_t base = uint64_t(blockIdx.x - r.first) * MERKLE_NODES + (threadIdx.x & ~63u);
+  if (base >= count) return;
+  const pos::MfLane L = pos::mf_lane(tab);
+  const uint64_t off_below = (uint64_t(2) << j.logN) - (uint64_t(2) << (level + 1));
+  const uint64_t off_here = (uint64_t(2) << j.logN) - (uint64_t(2) << level);
+  pos::merkle_nodes_mf(j.tree + off_below * DIGEST, count, base, j.tree + off_here * DIGEST, L, rc, tab,
+                       level == j.cap_height ? j.cap : nullptr);
 }
 
 // The same for depths with few nodes in all: 16 lanes per node (wide_permute).
@@ -340,8 +372,14 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
     if (ph.kind <= 3)
       hipLaunchKernelGGL(k_batch_pass, dim3(ph.blocks), dim3(lde::LDE_THREADS), ph.lds, cs, d_jobs, rr, nr, ph.kind,
                          tw);
+    else if (ph.kind == 4 && ctx->mf)
+      hipLaunchKernelGGL(k_batch_leaf_mf, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ctx->d_pos,
+                         ctx->d_mf);
     else if (ph.kind == 4)
       hipLaunchKernelGGL(k_batch_leaf, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ctx->d_pos, c);
+    else if (ph.kind == 5 && ctx->mf)
+      hipLaunchKernelGGL(k_batch_merkle_mf, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ph.depth,
+                         ctx->d_pos, ctx->d_mf);
     else if (ph.kind == 5)
       hipLaunchKernelGGL(k_batch_merkle, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ph.depth,
                          ctx->d_pos, c);

@@ -109,4 +109,43 @@ bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts) {
   return false;
 }
 
+// Matrix-core linear layer (poseidon_mf.h). Row of output i = 6h + ii (h = i / 6):
+// 8 (ii / 4) + 4h + ii % 4, where the 32x32 output layout puts it in the lanes that
+// hold words 6h .. 6h+5. Column of word j = 6h' + jj, part q: 16h' + 2jj + q, holding
+// ceil(C/2) (q = 0) or floor(C/2) (q = 1) of C = a[(j - i) mod 12]. Lane l holds row
+// l % 32, columns 16 (l / 32) .. +15 as 16 bytes. The accumulator start values are
+// K + (next round constant).lo and K + (next round constant).hi with
+// K = 128 (sum_j a_j) (2^24 + 2^16 + 2^8 + 1), which offsets the bytes' -128 shift.
+bool build_mf_table(const PoseidonTables &t, uint64_t out[MF_TABLE_WORDS]) {
+  memset(out, 0, MF_TABLE_WORDS * sizeof(uint64_t));
+  uint64_t R = 0;
+  for (int j = 0; j < WIDTH; j++) {
+    if (t.circ[j] > 254) return false;
+    R += t.circ[j];
+  }
+  int8_t A[32][32] = {};
+  for (int i = 0; i < WIDTH; i++) {
+    const int h = i / 6, ii = i % 6, row = 8 * (ii / 4) + 4 * h + ii % 4;
+    for (int j = 0; j < WIDTH; j++) {
+      const uint32_t C = t.circ[(j - i + WIDTH) % WIDTH];
+      const int col = 16 * (j / 6) + 2 * (j % 6);
+      A[row][col] = (int8_t)((C + 1) / 2);
+      A[row][col + 1] = (int8_t)(C / 2);
+    }
+  }
+  uint8_t *am = reinterpret_cast<uint8_t *>(out + MF_AMAT);
+  for (int l = 0; l < 64; l++)
+    for (int b = 0; b < 16; b++) am[l * 16 + b] = (uint8_t)A[l % 32][16 * (l / 32) + b];
+  int32_t *mult = reinterpret_cast<int32_t *>(out + MF_MULT);
+  for (int k = 0; k < 4; k++) mult[k] = 1 << (8 * k);
+  const uint64_t K = 128 * R * 0x01010101ull;
+  for (int r = 0; r <= ROUNDS; r++)
+    for (int i = 0; i < WIDTH; i++) {
+      const uint64_t c = r < ROUNDS ? t.rc[r][i] : 0;
+      out[MF_RCK + (size_t(r) * WIDTH + i) * 2] = K + (uint32_t)c;
+      out[MF_RCK + (size_t(r) * WIDTH + i) * 2 + 1] = K + (c >> 32);
+    }
+  return true;
+}
+
 }  // namespace v3db

@@ -20,6 +20,11 @@ constexpr int WIDTH = 12, RATE = 8, DIGEST = 4, ROUNDS = 30, FULL_HALF = 4;
 // Tree levels of at most this many nodes use 16 lanes per node (shorter latency).
 constexpr uint64_t MERKLE_WIDE_MAX_NODES = uint64_t(1) << 15;
 constexpr size_t POS_TABLE_WORDS = (ROUNDS + 1) * WIDTH + WIDTH * WIDTH / 2;
+// Table of the matrix-core linear layer (poseidon_mf.h), in 64-bit words: the int8
+// matrix as 16 bytes per lane, the four limb weights as int32, then (ROUNDS + 1) x
+// WIDTH pairs {lo, hi} of accumulator start values (row r + 1 used by round r).
+constexpr size_t MF_AMAT = 0, MF_MULT = 128, MF_RCK = 130;
+constexpr size_t MF_TABLE_WORDS = MF_RCK + size_t(ROUNDS + 1) * WIDTH * 2;
 constexpr int TW_LOG = 26;        // largest transform, 2^26 points
 constexpr int TW_HALF = 13;       // two-level twiddle table: 2^13 x 2^13
 constexpr int DFT_LOG_MAX = 12;   // largest in-LDS sub-transform, 4096 points
@@ -79,6 +84,8 @@ struct v3db_ctx {
   uint64_t *d_pos = nullptr;         // POS_TABLE_WORDS: round constants (ROUNDS + 1 rows, last zero),
                                     // then the matrix rows M[i][j] as 32-bit words
   const uint32_t *d_circ_rows = nullptr;  // inside d_pos
+  uint64_t *d_mf = nullptr;          // MF_TABLE_WORDS: the matrix-core linear layer's table
+  bool mf = false;                   // hash kernels use the matrix-core linear layer
   v3db::Twiddles tw{};
   std::map<std::tuple<uint32_t, uint32_t, uint64_t>, v3db::LdePlan> plans;
   std::map<std::pair<uint32_t, uint32_t>, v3db::LdeSchedule> tuned;  // autotuned schedules
@@ -120,6 +127,9 @@ v3db_status ctx_scratch(v3db_ctx *ctx, hipStream_t stream, size_t bytes, void **
 uint64_t splitmix64(uint64_t seed, uint64_t i);
 bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts);
 bool circulant_is_mds(const uint32_t circ[WIDTH]);
+// The matrix-core linear layer's table; false if an entry exceeds 254 (it would not
+// split into two int8 halves), in which case the hash kernels keep the VALU form.
+bool build_mf_table(const PoseidonTables &t, uint64_t out[MF_TABLE_WORDS]);
 
 // Tables (ntt.hip).
 v3db_status build_twiddles(v3db_ctx *ctx);

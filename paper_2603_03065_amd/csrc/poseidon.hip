@@ -1,6 +1,6 @@
 // Poseidon kernels for single calls: permutation of state arrays, leaf hashing
 // of a matrix, and one Merkle level per launch (routines in poseidon_dev.h).
-#include "poseidon_dev.h"
+#include "poseidon_mf.h"
 
 namespace v3db {
 
@@ -44,6 +44,28 @@ __global__ void __launch_bounds__(THREADS) k_merkle_level(const uint64_t *__rest
   merkle_node(below, k, above + k * DIGEST, rc, a);
 }
 
+// The same two kernels with the matrix-core linear layer: each wave covers 64
+// consecutive rows (nodes), a block of THREADS threads covers THREADS of them.
+__global__ void __launch_bounds__(THREADS) k_leaf_hash_mf(const uint64_t *__restrict__ mat, uint32_t n_cols,
+                                                          uint64_t n_rows, uint64_t *__restrict__ dig,
+                                                          const uint64_t *__restrict__ rc,
+                                                          const uint64_t *__restrict__ tab) {
+  const uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  if (base >= n_rows) return;  // whole waves only
+  const MfLane L = mf_lane(tab);
+  leaf_digests_mf(mat, n_cols, n_rows, base, dig, L, rc, tab);
+}
+
+__global__ void __launch_bounds__(THREADS) k_merkle_level_mf(const uint64_t *__restrict__ below,
+                                                             uint64_t *__restrict__ above, uint64_t count,
+                                                             const uint64_t *__restrict__ rc,
+                                                             const uint64_t *__restrict__ tab) {
+  const uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  if (base >= count) return;
+  const MfLane L = mf_lane(tab);
+  merkle_nodes_mf(below, count, base, above, L, rc, tab);
+}
+
 // One level with few nodes: 16 lanes per node (wide_permute).
 __global__ void __launch_bounds__(WIDE_THREADS) k_merkle_level_wide(const uint64_t *__restrict__ below,
                                                                     uint64_t *__restrict__ above, uint64_t count,
@@ -71,8 +93,12 @@ v3db_status enqueue_permute(v3db_ctx *ctx, uint64_t *states, size_t count, hipSt
 v3db_status enqueue_leaf_hash(v3db_ctx *ctx, const uint64_t *mat, uint32_t n_cols, uint32_t log_leaves,
                               uint64_t *digests, hipStream_t stream) {
   const uint64_t n = uint64_t(1) << log_leaves;
-  hipLaunchKernelGGL(k_leaf_hash, dim3(blocks_for(n)), dim3(THREADS), 0, stream, mat, n_cols, n, digests,
-                     ctx->d_pos, circ_of(ctx));
+  if (ctx->mf)
+    hipLaunchKernelGGL(k_leaf_hash_mf, dim3(blocks_for(n)), dim3(THREADS), 0, stream, mat, n_cols, n, digests,
+                       ctx->d_pos, ctx->d_mf);
+  else
+    hipLaunchKernelGGL(k_leaf_hash, dim3(blocks_for(n)), dim3(THREADS), 0, stream, mat, n_cols, n, digests,
+                       ctx->d_pos, circ_of(ctx));
   return hip_check(hipGetLastError(), "leaf hash launch");
 }
 
@@ -86,6 +112,9 @@ v3db_status enqueue_merkle_levels(v3db_ctx *ctx, uint64_t *tree, uint32_t log_le
       hipLaunchKernelGGL(k_merkle_level_wide, dim3((unsigned)((above + WIDE_PER_BLOCK - 1) / WIDE_PER_BLOCK)),
                          dim3(WIDE_THREADS), 0, stream, tree + off * DIGEST, tree + (off + cnt) * DIGEST, above,
                          ctx->d_pos, ctx->d_circ_rows);
+    else if (ctx->mf)
+      hipLaunchKernelGGL(k_merkle_level_mf, dim3(blocks_for(above)), dim3(THREADS), 0, stream, tree + off * DIGEST,
+                         tree + (off + cnt) * DIGEST, above, ctx->d_pos, ctx->d_mf);
     else
       hipLaunchKernelGGL(k_merkle_level, dim3(blocks_for(above)), dim3(THREADS), 0, stream, tree + off * DIGEST,
                          tree + (off + cnt) * DIGEST, above, ctx->d_pos, c);

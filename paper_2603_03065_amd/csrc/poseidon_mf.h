@@ -1,0 +1,218 @@
+// Width-12 Poseidon with the matrix product on the int8 matrix cores, for
+// kernels that hash many independent inputs (leaf rows, tree nodes, records).
+//
+// A wave holds 64 permutations. Lane l (h = l / 32, c = l % 32) keeps words
+// 6h .. 6h+5 of permutations c and c + 32, so each lane still holds 12 state
+// words. S-boxes run on those words as before; the partial rounds' single S-box
+// (word 0, held by the lanes with h = 0 for both permutations) is moved so that
+// every lane computes one: permutation c + 32's word goes to lane c + 32 and
+// back with v_permlane32_swap.
+//
+// The linear layer y_i = sum_j a[(j-i) mod 12] s_j is exact over the integers
+// before the reduction, and it is computed limb by limb: with b_jk byte k of s_j,
+//   y_i = sum_k 2^(8k) sum_j C_ij b_jk.
+// v_mfma_i32_32x32x32_i8 (signed bytes, int32 sums) forms sum_j C_ij b_jk for one
+// limb k of the 32 permutations of one half of the wave:
+//   * B column = one permutation; a lane supplies the K slots of its half
+//     (16h .. 16h+15), slot 2jj + part holding b'_jk = b_jk - 128 of its word jj
+//     (the byte XOR 0x80 read as signed) for both parts;
+//   * A row for output i holds ceil(C/2) in part 0 and floor(C/2) in part 1 of
+//     word j, so the two parts add to C (every entry must be at most 254 so the
+//     halves fit int8; the host checks and otherwise keeps the VALU form);
+//   * D row 8(e/4) + 4h + e%4 of column c lands in lane 32h + c, element e: the
+//     host puts output i = 6h + ii in row 8(ii/4) + 4h + ii%4, so each lane
+//     receives exactly the outputs for the words it holds (e = ii).
+// With b' = b - 128, sum_k 2^(8k) D_ik = y_i - 128 R G, R = sum_j C_ij (the same
+// for every row of a circulant) and G = sum_k 2^(8k). Each output accumulates
+// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ...,
+// K = 128 R (2^24 + 2^16 + 2^8 + 1) making both non-negative (D_ik >= -128 R) and
+// below 2^46, then fold(lo, hi) gives the relaxed output exactly as in the VALU
+// form. The start values K + next round's constant come from a small table.
+#pragma once
+#include "poseidon_dev.h"
+
+namespace v3db {
+namespace pos {
+
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+typedef int mf_v16i __attribute__((ext_vector_type(16)));
+
+struct MfLane {
+  mf_v4i A;     // this lane's 16 bytes of the matrix
+  int mult[4];  // 1, 2^8, 2^16, 2^24 read from the table: each term stays one v_mad_i64_i32
+  int h, c;
+};
+
+__device__ __forceinline__ MfLane mf_lane(const uint64_t *__restrict__ tab) {
+  MfLane L;
+  const int l = threadIdx.x & 63;
+  L.h = l >> 5;
+  L.c = l & 31;
+  const uint32_t *am = reinterpret_cast<const uint32_t *>(tab + MF_AMAT) + l * 4;
+#pragma unroll
+  for (int q = 0; q < 4; q++) L.A[q] = (int)am[q];
+  const int *m = reinterpret_cast<const int *>(tab + MF_MULT);
+#pragma unroll
+  for (int q = 0; q < 4; q++) L.mult[q] = m[q];
+  return L;
+}
+
+// permlane32 swap of 64-bit values: lanes < 32 keep a, lanes >= 32 get b from lane l - 32
+__device__ __forceinline__ uint64_t mf_up(uint64_t a, uint64_t b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+  return ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0];
+}
+// lanes < 32 get a from lane l + 32
+__device__ __forceinline__ uint64_t mf_down(uint64_t a) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)a, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(a >> 32), false, false);
+  return ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1];
+}
+
+// The permutation of the wave's 64 states (layout above). rc: the round-constant
+// rows (row 0 added first); tab: the table above. All 64 lanes must be active.
+__device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, const uint64_t *__restrict__ rc,
+                                           const uint64_t *__restrict__ tab) {
+  const int h = L.h;
+#pragma unroll
+  for (int u = 0; u < 2; u++)
+#pragma unroll
+    for (int jj = 0; jj < 6; jj++) S[u][jj] = gl::add_r(S[u][jj], rc[6 * h + jj]);
+#pragma unroll 1
+  for (int r = 0; r < ROUNDS; r++) {
+    const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int jj = 0; jj < 6; jj++) S[u][jj] = sbox(S[u][jj]);
+    } else {
+      const uint64_t y = sbox(mf_up(S[0][0], S[1][0]));
+      const uint64_t t = mf_down(y);
+      // selects, not a branch: a divergent branch here makes the compiler copy the state
+      S[0][0] = h == 0 ? y : S[0][0];
+      S[1][0] = h == 0 ? t : S[1][0];
+    }
+    const uint64_t *kr = tab + MF_RCK + (size_t(r + 1) * WIDTH + 6 * h) * 2;
+    uint32_t dw[2][6][2];
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+      for (int jj = 0; jj < 6; jj++) {
+        dw[u][jj][0] = (uint32_t)S[u][jj] ^ 0x80808080u;
+        dw[u][jj][1] = (uint32_t)(S[u][jj] >> 32) ^ 0x80808080u;
+      }
+    int64_t lo[2][6], hi[2][6];
+#pragma unroll
+    for (int ii = 0; ii < 6; ii++) {
+      lo[0][ii] = lo[1][ii] = (int64_t)kr[2 * ii];
+      hi[0][ii] = hi[1][ii] = (int64_t)kr[2 * ii + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint32_t kk = k & 3, half = k >> 2;
+      // bytes kk of two words, each twice (parts 0 and 1): v_perm selectors 0-3 pick
+      // from the second source, 4-7 from the first
+      const uint32_t sel = kk | (kk << 8) | ((kk + 4) << 16) | ((kk + 4) << 24);
+      mf_v16i D[2];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        mf_v4i B;
+        B[0] = (int)__builtin_amdgcn_perm(dw[u][1][half], dw[u][0][half], sel);
+        B[1] = (int)__builtin_amdgcn_perm(dw[u][3][half], dw[u][2][half], sel);
+        B[2] = (int)__builtin_amdgcn_perm(dw[u][5][half], dw[u][4][half], sel);
+        B[3] = 0;
+        D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A, B, (mf_v16i){}, 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int ii = 0; ii < 6; ii++) {
+          if (k < 4) lo[u][ii] += (int64_t)D[u][ii] * (int64_t)L.mult[kk];
+          else hi[u][ii] += (int64_t)D[u][ii] * (int64_t)L.mult[kk];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+      for (int ii = 0; ii < 6; ii++) S[u][ii] = fold((uint64_t)lo[u][ii], (uint64_t)hi[u][ii]);
+  }
+}
+
+// Rate-8 overwrite sponge over len elements for the wave's 64 inputs: elem(u, x)
+// gives element x of input c + 32u (called only for x < len, and only by lanes
+// whose input exists when `live(u)`; others absorb zeros). Leaves the state in S.
+template <typename Elem, typename Live>
+__device__ __forceinline__ void sponge_mf(uint64_t S[2][6], uint64_t len, Elem elem, Live live, const MfLane &L,
+                                          const uint64_t *__restrict__ rc, const uint64_t *__restrict__ tab) {
+#pragma unroll
+  for (int u = 0; u < 2; u++)
+#pragma unroll
+    for (int jj = 0; jj < 6; jj++) S[u][jj] = 0;
+  for (uint64_t q = 0; q < len; q += RATE) {
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+      for (int jj = 0; jj < 6; jj++) {
+        const int j = 6 * L.h + jj;
+        if (j < RATE && q + j < len) S[u][jj] = live(u) ? elem(u, q + j) : 0;
+      }
+    permute_mf(S, L, rc, tab);
+  }
+}
+
+// Write the digests (words 0..3, held by the lanes with h = 0) of the wave's
+// inputs base + c + 32u that are below count, canonical, to out[input * 4 + w]
+// (and to out2 as well unless it is null).
+__device__ __forceinline__ void store_digests_mf(const uint64_t S[2][6], const MfLane &L, uint64_t base,
+                                                 uint64_t count, uint64_t *__restrict__ out,
+                                                 uint64_t *__restrict__ out2 = nullptr) {
+  if (L.h != 0) return;
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    const uint64_t k = base + L.c + 32 * u;
+    if (k < count) {
+#pragma unroll
+      for (int w = 0; w < DIGEST; w++) {
+        const uint64_t v = gl::canon(S[u][w]);
+        out[k * DIGEST + w] = v;
+        if (out2) out2[k * DIGEST + w] = v;
+      }
+    }
+  }
+}
+
+// Leaf digests of rows base .. base+63 of a column-major matrix with n_rows rows.
+__device__ __forceinline__ void leaf_digests_mf(const uint64_t *__restrict__ mat, uint32_t n_cols, uint64_t n_rows,
+                                                uint64_t base, uint64_t *__restrict__ out, const MfLane &L,
+                                                const uint64_t *__restrict__ rc, const uint64_t *__restrict__ tab,
+                                                uint64_t *__restrict__ out2 = nullptr) {
+  uint64_t S[2][6];
+  sponge_mf(
+      S, n_cols, [&](int u, uint64_t x) { return mat[x * n_rows + base + L.c + 32 * u]; },
+      [&](int u) { return base + L.c + 32 * u < n_rows; }, L, rc, tab);
+  store_digests_mf(S, L, base, n_rows, out, out2);
+}
+
+// Nodes base .. base+63 of a level: node k = Compress(below[2k], below[2k+1]).
+__device__ __forceinline__ void merkle_nodes_mf(const uint64_t *__restrict__ below, uint64_t count, uint64_t base,
+                                                uint64_t *__restrict__ out, const MfLane &L,
+                                                const uint64_t *__restrict__ rc, const uint64_t *__restrict__ tab,
+                                                uint64_t *__restrict__ out2 = nullptr) {
+  uint64_t S[2][6];
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    const uint64_t k = base + L.c + 32 * u;
+#pragma unroll
+    for (int jj = 0; jj < 6; jj++) {
+      const int j = 6 * L.h + jj;
+      S[u][jj] = (j < 2 * DIGEST && k < count) ? below[k * 2 * DIGEST + j] : 0;
+    }
+  }
+  permute_mf(S, L, rc, tab);
+  store_digests_mf(S, L, base, count, out, out2);
+}
+
+}  // namespace pos
+}  // namespace v3db

@@ -5,7 +5,7 @@
 // a Merkle tree over those digests, and a digest of the PQ codebooks. The
 // codebook digest is one long sequential sponge; it runs on a side stream,
 // forked from and joined back into the caller's stream, beside the rest.
-#include "poseidon_dev.h"
+#include "poseidon_mf.h"
 
 namespace v3db {
 
@@ -39,6 +39,24 @@ __global__ void __launch_bounds__(LEAF_THREADS)
   }
 #pragma unroll
   for (int w = 0; w < DIGEST; w++) digests[t * DIGEST + w] = gl::canon(s[w]);
+}
+
+// The same with the matrix-core linear layer: each wave covers 64 consecutive records.
+__global__ void __launch_bounds__(LEAF_THREADS)
+    k_snap_leaf_mf(const uint64_t *__restrict__ flag, const uint64_t *__restrict__ item,
+                   const uint64_t *__restrict__ codes, uint32_t m, uint32_t log_slots, uint64_t n_rec,
+                   uint64_t *__restrict__ digests, const uint64_t *__restrict__ rc, const uint64_t *__restrict__ tab) {
+  const uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  if (base >= n_rec) return;  // whole waves only
+  const MfLane L = mf_lane(tab);
+  const uint64_t mask = (uint64_t(1) << log_slots) - 1;
+  auto elem = [&](int u, uint64_t x) -> uint64_t {
+    const uint64_t t = base + L.c + 32 * u;
+    return x == 0 ? t >> log_slots : x == 1 ? t & mask : x == 2 ? flag[t] : x == 3 ? item[t] : codes[(x - 4) * n_rec + t];
+  };
+  uint64_t S[2][6];
+  sponge_mf(S, 4 + uint64_t(m), elem, [&](int u) { return base + L.c + 32 * u < n_rec; }, L, rc, tab);
+  store_digests_mf(S, L, base, n_rec, digests);
 }
 
 // hash_i = Hash(i, mu_i[0..D-1], root_i), 16 lanes per list.
@@ -99,8 +117,13 @@ v3db_status enqueue_snapshot(v3db_ctx *ctx, uint32_t log_lists, uint32_t log_slo
   e = hipGetLastError();
   if (e == hipSuccess) e = hipEventRecord(ctx->join_ev, ctx->side_stream);
   if (e != hipSuccess) return hip_check(e, "snapshot codebook digest");
-  hipLaunchKernelGGL(k_snap_leaf, dim3((unsigned)((N + LEAF_THREADS - 1) / LEAF_THREADS)), dim3(LEAF_THREADS), 0,
-                     stream, flag, item, codes, m, log_slots, N, tree, ctx->d_pos, circ_of(ctx));
+  const unsigned leaf_blocks = (unsigned)((N + LEAF_THREADS - 1) / LEAF_THREADS);
+  if (ctx->mf)
+    hipLaunchKernelGGL(k_snap_leaf_mf, dim3(leaf_blocks), dim3(LEAF_THREADS), 0, stream, flag, item, codes, m,
+                       log_slots, N, tree, ctx->d_pos, ctx->d_mf);
+  else
+    hipLaunchKernelGGL(k_snap_leaf, dim3(leaf_blocks), dim3(LEAF_THREADS), 0, stream, flag, item, codes, m,
+                       log_slots, N, tree, ctx->d_pos, circ_of(ctx));
   v3db_status st = hip_check(hipGetLastError(), "snapshot leaves");
   // list roots = the level of the record tree at height log2(n_list)
   if (st == V3DB_OK) st = enqueue_merkle_levels(ctx, tree, log_lists + log_slots, log_lists, list_roots, stream);

@@ -1,0 +1,133 @@
+"""GPU: the two forms of the permutation's linear layer in the bulk hashing
+kernels, int8 matrix cores (every circulant entry at most 254, the default seed
+included) and VALU multiply-adds (a circulant with an entry of 255, or
+V3DB_POSEIDON_VALU=1), each equal to the oracle and to each other word for word:
+leaf rows with ragged column counts, tree levels wide enough for the
+one-node-per-lane kernels, batch phases with traces of fewer rows than a wave,
+snapshot records and FRI trees."""
+import numpy as np
+import pytest
+
+from paper_2603_03065_amd import inputs
+
+pytestmark = pytest.mark.gpu
+P = inputs.P
+DEFAULT_SEED = 260303065
+SEED_255 = 53  # its circulant (found by search over seeds) has 255 as its last entry
+
+
+@pytest.fixture(scope="module")
+def v3db():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2603_03065_amd as m
+    m.lib()
+    return m
+
+
+def _host(v3db, t):
+    import torch
+    torch.cuda.synchronize()
+    return v3db.to_host(t)
+
+
+def _run_all(v3db, ctx):
+    """Every bulk hashing entry point on small seeded inputs; host copies of the outputs."""
+    import torch
+    out = {}
+    # a commit whose tree has levels of 2^16 and 2^15 nodes (both Merkle kernels), 11 columns
+    tr = inputs.trace(61, 0, 11, 14)
+    job = v3db.Job(trace=v3db.to_device(tr), log_blowup=3, cap_height=3,
+                   lde=torch.empty((11, 1 << 17), dtype=torch.int64, device="cuda"),
+                   tree=torch.empty(((2 << 17) - 8, 4), dtype=torch.int64, device="cuda"))
+    ctx.commit(job)
+    out["commit_tree"], out["commit_cap"] = _host(v3db, job.tree), _host(v3db, job.cap)
+    # leaf hashing of a matrix with fewer rows than a wave, 13 columns
+    mat = inputs.trace(62, 0, 13, 5)
+    tree = torch.empty((2 * 32 - 1, 4), dtype=torch.int64, device="cuda")
+    cap = ctx.merkle_commit(v3db.to_device(mat), 0, tree=tree)
+    out["small_tree"], out["small_cap"] = _host(v3db, tree), _host(v3db, cap)
+    # a batch: one trace of 2^17 extended rows (so depths 1 and 2 of the batch run one node
+    # per lane) and traces of 2^4 .. 2^6 extended rows (partial waves in every phase)
+    trs = [inputs.trace(63, 0, 9, 14)] + [inputs.trace(63, t, 3 + 5 * t, t) for t in range(1, 4)]
+    jobs = []
+    for t in trs:
+        C, n = t.shape
+        N = n << 3
+        h = min(2, N.bit_length() - 1)
+        jobs.append(v3db.Job(trace=v3db.to_device(t), log_blowup=3, cap_height=h,
+                             lde=torch.empty((C, N), dtype=torch.int64, device="cuda"),
+                             tree=torch.empty((2 * N - (1 << h), 4), dtype=torch.int64, device="cuda")))
+    ctx.commit_batch(jobs)
+    out["batch"] = [(_host(v3db, j.tree), _host(v3db, j.cap)) for j in jobs]
+    # snapshot: 2^17 records of M = 8 codes (12-element records: two permutations each)
+    shape = (5, 12, 8, 16, 4)
+    s = inputs.snapshot(64, *shape)
+    d = {k: v3db.to_device(np.ascontiguousarray(v)) for k, v in s.items()}
+    mk, cb, roots = ctx.snapshot_commit(*shape, d["flag"], d["item"], d["codes"], d["centroids"], d["codebooks"])
+    out["snapshot"] = (_host(v3db, mk), _host(v3db, cb), _host(v3db, roots))
+    # FRI over 2^18 points: round 0's tree has 2^17 leaves and a 2^16-node level
+    f0 = inputs.canon(inputs.splitmix64(65, np.arange(1 << 18, dtype=np.uint64)))
+    betas = [int(b) % P for b in inputs.splitmix64(66, np.arange(6, dtype=np.uint64))]
+    folded, caps, trees = ctx.fri_commit(v3db.to_device(f0), 7, betas, 2, want_trees=True)
+    out["fri"] = (_host(v3db, folded), _host(v3db, caps), _host(v3db, trees))
+    return out, (tr, mat, trs, shape, s, f0, betas)
+
+
+def _check_against_oracle(got, ins, pos):
+    tr, mat, trs, shape, s, f0, betas = ins
+    cap, _, tree = pos.commit(tr, 3, 7, 0, 3, want_tree=True)
+    assert np.array_equal(got["commit_tree"], tree) and np.array_equal(got["commit_cap"], cap)
+    ocap, otree = pos.merkle_commit(mat, 0, want_tree=True)
+    assert np.array_equal(got["small_cap"], ocap) and np.array_equal(got["small_tree"], otree)
+    for t, (gtree, gcap) in zip(trs, got["batch"]):
+        h = min(2, (t.shape[1] << 3).bit_length() - 1)
+        c, _, tr_ = pos.commit(t, 3, 7, 0, h, want_tree=True)
+        assert np.array_equal(gtree, tr_) and np.array_equal(gcap, c)
+    mk, cb, roots, _ = pos.snapshot_commit(*shape, s["flag"], s["item"], s["codes"], s["centroids"], s["codebooks"])
+    assert np.array_equal(got["snapshot"][0], mk) and np.array_equal(got["snapshot"][1], cb)
+    assert np.array_equal(got["snapshot"][2], roots)
+    ofolded, ocaps, otrees = pos.fri_commit(f0, 7, betas, 2, want_trees=True)
+    assert np.array_equal(got["fri"][0], ofolded) and np.array_equal(got["fri"][1], ocaps)
+    assert np.array_equal(got["fri"][2], otrees)
+
+
+def test_path_selection(v3db, monkeypatch):
+    with v3db.Context(0) as c:
+        assert c.hash_path == "mfma"
+    with v3db.Context(0, seed=SEED_255) as c:
+        assert c.hash_path == "valu"
+    monkeypatch.setenv("V3DB_POSEIDON_VALU", "1")
+    with v3db.Context(0) as c:
+        assert c.hash_path == "valu"
+    monkeypatch.setenv("V3DB_POSEIDON_VALU", "0")
+    with v3db.Context(0) as c:
+        assert c.hash_path == "mfma"
+
+
+def test_matrix_cores_and_valu_agree_with_oracle(v3db, poseidon, oracle_mod, monkeypatch):
+    oracle_mod.set_threads(0)
+    with v3db.Context(0) as c:
+        got_mf, ins = _run_all(v3db, c)
+    monkeypatch.setenv("V3DB_POSEIDON_VALU", "1")
+    with v3db.Context(0) as c:
+        assert c.hash_path == "valu"
+        got_valu, _ = _run_all(v3db, c)
+    for k in got_mf:
+        a, b = got_mf[k], got_valu[k]
+        if isinstance(a, list):
+            assert all(np.array_equal(x, y) for p, q in zip(a, b) for x, y in zip(p, q)), k
+        elif isinstance(a, tuple):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), k
+        else:
+            assert np.array_equal(a, b), k
+    _check_against_oracle(got_mf, ins, poseidon)
+
+
+def test_circulant_with_255_falls_back_and_matches_oracle(v3db, oracle_mod):
+    oracle_mod.set_threads(0)
+    pos = oracle_mod.Poseidon(SEED_255)
+    with v3db.Context(0, seed=SEED_255) as c:
+        assert c.hash_path == "valu"
+        got, ins = _run_all(v3db, c)
+    _check_against_oracle(got, ins, pos)
