@@ -145,6 +145,31 @@ __global__ void __launch_bounds__(POS_THREADS) k_batch_merkle_mf(const BJob *__r
                        level == j.cap_height ? j.cap : nullptr);
 }
 
+// The same for depths with very few nodes in all: 32 lanes per node (pair_permute).
+__global__ void __launch_bounds__(pos::PAIR_THREADS) k_batch_merkle_pair(const BJob *__restrict__ jobs,
+                                                                         const BRange *__restrict__ ranges,
+                                                                         int n_ranges, int depth,
+                                                                         const uint64_t *__restrict__ rc,
+                                                                         const uint32_t *__restrict__ circ_rows) {
+  const BRange r = ranges[find_range(ranges, n_ranges, blockIdx.x)];
+  const BJob &j = jobs[r.job];
+  const uint32_t level = j.logN - depth;
+  const uint64_t count = uint64_t(1) << level;
+  const int q = threadIdx.x % pos::PAIR_GROUP, grp = threadIdx.x / pos::PAIR_GROUP, g = q & 15;
+  const uint64_t k = uint64_t(blockIdx.x - r.first) * pos::PAIR_PER_BLOCK + grp;
+  const bool live = k < count;
+  const uint64_t off_below = (uint64_t(2) << j.logN) - (uint64_t(2) << (level + 1));
+  const uint64_t off_here = (uint64_t(2) << j.logN) - (uint64_t(2) << level);
+  uint64_t s = 0;
+  if (live && g < 2 * DIGEST) s = j.tree[(off_below + 2 * k) * DIGEST + g];
+  s = pos::pair_permute(s, q, rc, circ_rows);
+  if (live && q < DIGEST) {
+    const uint64_t v = gl::canon(s);
+    j.tree[(off_here + k) * DIGEST + q] = v;
+    if (level == j.cap_height) j.cap[k * DIGEST + q] = v;
+  }
+}
+
 // The same for depths with few nodes in all: 16 lanes per node (wide_permute).
 __global__ void __launch_bounds__(pos::WIDE_THREADS) k_batch_merkle_wide(const BJob *__restrict__ jobs,
                                                                          const BRange *__restrict__ ranges,
@@ -237,7 +262,7 @@ v3db_status commit_single(v3db_ctx *ctx, const v3db_commit_job &j, void *scratch
 }
 
 struct Phase {
-  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth, 6 Merkle depth with 16 lanes per node
+  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth, 6 (7) Merkle depth with 16 (32) lanes per node
   int depth;  // Merkle depth
   size_t ranges_off, n_ranges;
   uint32_t blocks;
@@ -294,9 +319,9 @@ void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3d
     uint64_t total = 0;
     for (size_t i = 0; i < nj; i++) total += nodes_of(i);
     // few nodes at this depth in all: 16 lanes per node for a shorter chain
-    const bool wide = total <= MERKLE_WIDE_MAX_NODES;
-    const uint64_t per_block = wide ? pos::WIDE_PER_BLOCK : MERKLE_NODES;
-    add_phase(wide ? 6 : 5, (int)d, 0,
+    const bool pair = total <= MERKLE_PAIR_MAX_NODES, wide = total <= MERKLE_WIDE_MAX_NODES;
+    const uint64_t per_block = pair ? pos::PAIR_PER_BLOCK : wide ? pos::WIDE_PER_BLOCK : MERKLE_NODES;
+    add_phase(pair ? 7 : wide ? 6 : 5, (int)d, 0,
               [&](size_t i) -> uint32_t { return (uint32_t)((nodes_of(i) + per_block - 1) / per_block); });
   }
 }
@@ -383,6 +408,9 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
     else if (ph.kind == 5)
       hipLaunchKernelGGL(k_batch_merkle, dim3(ph.blocks), dim3(POS_THREADS), 0, cs, d_jobs, rr, nr, ph.depth,
                          ctx->d_pos, c);
+    else if (ph.kind == 7)
+      hipLaunchKernelGGL(k_batch_merkle_pair, dim3(ph.blocks), dim3(pos::PAIR_THREADS), 0, cs, d_jobs, rr, nr,
+                         ph.depth, ctx->d_pos, ctx->d_circ_rows);
     else
       hipLaunchKernelGGL(k_batch_merkle_wide, dim3(ph.blocks), dim3(pos::WIDE_THREADS), 0, cs, d_jobs, rr, nr,
                          ph.depth, ctx->d_pos, ctx->d_circ_rows);

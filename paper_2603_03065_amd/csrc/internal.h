@@ -19,6 +19,8 @@ constexpr int WIDTH = 12, RATE = 8, DIGEST = 4, ROUNDS = 30, FULL_HALF = 4;
 // 32-bit matrix entries (half as many 64-bit words).
 // Tree levels of at most this many nodes use 16 lanes per node (shorter latency).
 constexpr uint64_t MERKLE_WIDE_MAX_NODES = uint64_t(1) << 15;
+// ... and levels of at most this many, latency-bound, 32 lanes per node.
+constexpr uint64_t MERKLE_PAIR_MAX_NODES = uint64_t(1) << 11;
 constexpr size_t POS_TABLE_WORDS = (ROUNDS + 1) * WIDTH + WIDTH * WIDTH / 2;
 // Table of the matrix-core linear layer (poseidon_mf.h), in 64-bit words: the int8
 // matrix as 16 bytes per lane, the four limb weights as int32, then (ROUNDS + 1) x

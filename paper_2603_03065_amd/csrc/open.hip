@@ -33,42 +33,49 @@ __global__ void __launch_bounds__(GATHER_THREADS)
   }
 }
 
-// One query per group of 16 lanes (wide_permute): the row's sponge, then one
+// One query per group of 16 lanes (wide_permute) or, for few queries, of 32 lanes
+// (pair_permute: the chains are then latency-bound): the row's sponge, then one
 // compression per path level with the running node on the side the index bit
-// gives, then the comparison with the cap entry above the leaf.
-__global__ void __launch_bounds__(pos::WIDE_THREADS)
+// gives, then the comparison with the cap entry above the leaf. In the 32-lane
+// form both rows of a group hold the state; the even row's lanes write the shared
+// values.
+template <bool PAIR>
+__global__ void __launch_bounds__(64)
     k_verify(const uint64_t *__restrict__ rows, uint32_t n_cols, uint32_t log_leaves, uint32_t cap_height,
              const uint64_t *__restrict__ idx, uint64_t n_q, const uint64_t *__restrict__ paths,
              const uint64_t *__restrict__ cap, uint32_t *__restrict__ ok, const uint64_t *__restrict__ rc,
              const uint32_t *__restrict__ circ_rows) {
   using namespace pos;
-  __shared__ uint64_t node[WIDE_PER_BLOCK][DIGEST];
-  __shared__ uint32_t match[WIDE_PER_BLOCK][DIGEST];
-  const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
-  const uint64_t q = uint64_t(blockIdx.x) * WIDE_PER_BLOCK + grp;
-  const bool live = q < n_q;
-  const uint64_t index = live ? (idx[q] & ((uint64_t(1) << log_leaves) - 1)) : 0;
+  constexpr int GROUP = PAIR ? PAIR_GROUP : WIDE_GROUP, PER_BLOCK = 64 / GROUP;
+  __shared__ uint64_t node[PER_BLOCK][DIGEST];
+  __shared__ uint32_t match[PER_BLOCK][DIGEST];
+  const int q = threadIdx.x % GROUP, grp = threadIdx.x / GROUP, g = q & 15;
+  const uint64_t qi = uint64_t(blockIdx.x) * PER_BLOCK + grp;
+  const bool live = qi < n_q;
+  const uint64_t index = live ? (idx[qi] & ((uint64_t(1) << log_leaves) - 1)) : 0;
   const uint32_t depth = log_leaves - cap_height;
+  auto perm = [&](uint64_t x) { return PAIR ? pair_permute(x, q, rc, circ_rows) : wide_permute(x, g, rc, circ_rows); };
   // leaf: overwrite sponge over the row, 8 elements per permutation
   uint64_t s = 0;
   for (uint32_t c0 = 0; c0 < n_cols; c0 += RATE) {
-    if (g < RATE && c0 + g < n_cols) s = live ? rows[q * n_cols + c0 + g] : 0;
-    s = wide_permute(s, g, rc, circ_rows);
+    if (g < RATE && c0 + g < n_cols) s = live ? rows[qi * n_cols + c0 + g] : 0;
+    s = perm(s);
   }
   for (uint32_t l = 0; l < depth; l++) {
-    if (g < DIGEST) node[grp][g] = s;
+    if (q < DIGEST) node[grp][q] = s;
     __syncthreads();
-    const uint64_t *sib = paths + (q * depth + l) * DIGEST;
+    const uint64_t *sib = paths + (qi * depth + l) * DIGEST;
     const bool right = (index >> l) & 1;  // the running node is the right child
     if (g < DIGEST) s = right ? (live ? sib[g] : 0) : node[grp][g];
     else if (g < 2 * DIGEST) s = right ? node[grp][g - DIGEST] : (live ? sib[g - DIGEST] : 0);
     else s = 0;
-    s = wide_permute(s, g, rc, circ_rows);
+    __syncthreads();
+    s = perm(s);
   }
   const uint64_t ci = index >> depth;
-  if (g < DIGEST) match[grp][g] = live && gl::canon(s) == cap[ci * DIGEST + g];
+  if (q < DIGEST) match[grp][q] = live && gl::canon(s) == cap[ci * DIGEST + q];
   __syncthreads();
-  if (live && g == 0) ok[q] = match[grp][0] & match[grp][1] & match[grp][2] & match[grp][3];
+  if (live && q == 0) ok[qi] = match[grp][0] & match[grp][1] & match[grp][2] & match[grp][3];
 }
 
 unsigned grid_for(uint64_t items, int threads) {
@@ -93,9 +100,15 @@ v3db_status enqueue_verify(v3db_ctx *ctx, const uint64_t *rows, uint32_t n_cols,
                            uint32_t cap_height, const uint64_t *idx, size_t n_q, const uint64_t *paths,
                            const uint64_t *cap, uint32_t *ok, hipStream_t stream) {
   if (n_q == 0) return V3DB_OK;
-  const unsigned blocks = (unsigned)((n_q + pos::WIDE_PER_BLOCK - 1) / pos::WIDE_PER_BLOCK);
-  hipLaunchKernelGGL(k_verify, dim3(blocks), dim3(pos::WIDE_THREADS), 0, stream, rows, n_cols, log_leaves,
-                     cap_height, idx, (uint64_t)n_q, paths, cap, ok, ctx->d_pos, ctx->d_circ_rows);
+  if (n_q <= MERKLE_PAIR_MAX_NODES) {
+    const unsigned blocks = (unsigned)((n_q + pos::PAIR_PER_BLOCK - 1) / pos::PAIR_PER_BLOCK);
+    hipLaunchKernelGGL(k_verify<true>, dim3(blocks), dim3(64), 0, stream, rows, n_cols, log_leaves, cap_height, idx,
+                       (uint64_t)n_q, paths, cap, ok, ctx->d_pos, ctx->d_circ_rows);
+  } else {
+    const unsigned blocks = (unsigned)((n_q + pos::WIDE_PER_BLOCK - 1) / pos::WIDE_PER_BLOCK);
+    hipLaunchKernelGGL(k_verify<false>, dim3(blocks), dim3(64), 0, stream, rows, n_cols, log_leaves, cap_height, idx,
+                       (uint64_t)n_q, paths, cap, ok, ctx->d_pos, ctx->d_circ_rows);
+  }
   return hip_check(hipGetLastError(), "verify launch");
 }
 

@@ -66,6 +66,20 @@ __global__ void __launch_bounds__(THREADS) k_merkle_level_mf(const uint64_t *__r
   merkle_nodes_mf(below, count, base, above, L, rc, tab);
 }
 
+// One level with very few nodes: 32 lanes per node (pair_permute).
+__global__ void __launch_bounds__(PAIR_THREADS) k_merkle_level_pair(const uint64_t *__restrict__ below,
+                                                                    uint64_t *__restrict__ above, uint64_t count,
+                                                                    const uint64_t *__restrict__ rc,
+                                                                    const uint32_t *__restrict__ circ_rows) {
+  const int q = threadIdx.x % PAIR_GROUP, grp = threadIdx.x / PAIR_GROUP, g = q & 15;
+  const uint64_t k = uint64_t(blockIdx.x) * PAIR_PER_BLOCK + grp;
+  const bool live = k < count;
+  uint64_t s = 0;
+  if (live && g < 2 * DIGEST) s = below[k * 2 * DIGEST + g];
+  s = pair_permute(s, q, rc, circ_rows);
+  if (live && q < DIGEST) above[k * DIGEST + q] = gl::canon(s);
+}
+
 // One level with few nodes: 16 lanes per node (wide_permute).
 __global__ void __launch_bounds__(WIDE_THREADS) k_merkle_level_wide(const uint64_t *__restrict__ below,
                                                                     uint64_t *__restrict__ above, uint64_t count,
@@ -108,7 +122,11 @@ v3db_status enqueue_merkle_levels(v3db_ctx *ctx, uint64_t *tree, uint32_t log_le
   uint64_t off = 0, cnt = uint64_t(1) << log_leaves;
   for (uint32_t lvl = log_leaves; lvl > cap_height; lvl--) {
     const uint64_t above = cnt / 2;
-    if (above <= MERKLE_WIDE_MAX_NODES)
+    if (above <= MERKLE_PAIR_MAX_NODES)
+      hipLaunchKernelGGL(k_merkle_level_pair, dim3((unsigned)((above + PAIR_PER_BLOCK - 1) / PAIR_PER_BLOCK)),
+                         dim3(PAIR_THREADS), 0, stream, tree + off * DIGEST, tree + (off + cnt) * DIGEST, above,
+                         ctx->d_pos, ctx->d_circ_rows);
+    else if (above <= MERKLE_WIDE_MAX_NODES)
       hipLaunchKernelGGL(k_merkle_level_wide, dim3((unsigned)((above + WIDE_PER_BLOCK - 1) / WIDE_PER_BLOCK)),
                          dim3(WIDE_THREADS), 0, stream, tree + off * DIGEST, tree + (off + cnt) * DIGEST, above,
                          ctx->d_pos, ctx->d_circ_rows);

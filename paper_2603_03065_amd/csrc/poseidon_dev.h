@@ -239,5 +239,99 @@ inline Circ circ_of(const v3db_ctx *ctx) {
   return c;
 }
 
+// Permutation by 32 lanes (two 16-lane rows), for work bound by one permutation's
+// latency (a long sponge, a query's authentication path, the top levels of a
+// tree): a single wave then issues every instruction of the chain in turn, so
+// what counts is the number of instructions per lane per round. Both rows hold
+// the state (lane g < 12 of each row holds word g). Per round:
+//   * S-box: every lane forms x^2, the even row x^3 and the odd row x^4, the two
+//     are exchanged with v_permlane16_swap and multiplied (three products per
+//     lane instead of the four of x^7 on one lane; in partial rounds x is word 0
+//     broadcast over the row and only lane 0 keeps the result);
+//   * matrix product: the even row forms, for every output, the terms of words
+//     0..5 and the odd row those of words 6..11 (moved to its lanes 0..5 by a row
+//     shift), six broadcasts and twelve multiply-adds per lane instead of twelve
+//     and twenty-four; the two halves are added across the rows with
+//     v_permlane16_swap and folded as in wide_permute.
+// Used where few permutations run at once; with many, the 16-lane form does less
+// work in all. All 64 lanes of the wave must be active.
+constexpr int PAIR_GROUP = 32;
+constexpr int PAIR_THREADS = 64;  // one wave: 2 permutations
+constexpr int PAIR_PER_BLOCK = PAIR_THREADS / PAIR_GROUP;
+
+// v on the even row and v on the odd row of this lane's row pair, at every lane
+__device__ __forceinline__ void rows_both(uint64_t v, uint64_t &even, uint64_t &odd) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)v, (uint32_t)v, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
+  even = ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0];
+  odd = ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1];
+}
+
+// lane i of each row receives lane i + 6 of the row (DPP row_shl:6; lanes 10..15 get 0)
+__device__ __forceinline__ uint64_t row_shl6(uint64_t v) {
+  return (uint64_t)__builtin_amdgcn_update_dpp((long)0, (long)v, 0x106, 0xf, 0xf, false);
+}
+
+template <int J>
+__device__ __forceinline__ void pair_term(uint64_t src, const uint32_t m[6], uint64_t &al, uint64_t &ah) {
+  const uint64_t v = row_bcast<J>(src);
+  al += (uint64_t)m[J] * (uint32_t)v;
+  ah += (uint64_t)m[J] * (uint32_t)(v >> 32);
+}
+
+__device__ __forceinline__ uint64_t pair_permute(uint64_t s, int q, const uint64_t *__restrict__ rc,
+                                                 const uint32_t *__restrict__ circ_rows) {
+  const int g = q & 15, odd = q >> 4;
+  const int gi = g < WIDTH ? g : 0;
+  uint32_t m[6];  // this lane's half row of the matrix: entries 6 odd .. 6 odd + 5 of row gi
+#pragma unroll
+  for (int j = 0; j < 6; j++) m[j] = circ_rows[gi * WIDTH + 6 * odd + j];
+  s = gl::add_r(s, rc[gi]);
+  uint64_t rcn = rc[WIDTH + gi];
+#pragma unroll 1
+  for (int r = 0; r < ROUNDS; r++) {
+    const uint64_t rc_next = rcn;
+    if (r + 1 < ROUNDS) rcn = rc[(r + 2) * WIDTH + gi];
+    const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
+    const uint64_t x = full ? s : row_bcast<0>(s);
+    const uint64_t x2 = gl::mul_r_lat(x, x);
+    const uint64_t y = gl::mul_r_lat(x2, odd ? x2 : x);
+    uint64_t y_even, y_odd;
+    rows_both(y, y_even, y_odd);
+    const uint64_t x7 = gl::mul_r_lat(y_even, y_odd);
+    s = (full || g == 0) ? x7 : s;
+    const uint64_t t = row_shl6(s);
+    const uint64_t src = odd ? t : s;
+    uint64_t al = odd ? 0 : (uint32_t)rc_next, ah = odd ? 0 : rc_next >> 32;
+    pair_term<0>(src, m, al, ah);
+    pair_term<1>(src, m, al, ah);
+    pair_term<2>(src, m, al, ah);
+    pair_term<3>(src, m, al, ah);
+    pair_term<4>(src, m, al, ah);
+    pair_term<5>(src, m, al, ah);
+    uint64_t al_e, al_o, ah_e, ah_o;
+    rows_both(al, al_e, al_o);
+    rows_both(ah, ah_e, ah_o);
+    s = fold(al_e + al_o, ah_e + ah_o);
+  }
+  return s;
+}
+
+// Rate-8 overwrite sponge over len words by a group of 32 lanes (pair_permute);
+// elem(x) gives word x and is called only by live lanes with q % 16 < 8. Lane
+// q % 16 < 12 returns state word q % 16.
+template <class Elem>
+__device__ __forceinline__ uint64_t pair_sponge(uint64_t len, bool live, Elem elem, int q,
+                                                const uint64_t *__restrict__ rc,
+                                                const uint32_t *__restrict__ circ_rows) {
+  const int g = q & 15;
+  uint64_t s = 0;
+  for (uint64_t c0 = 0; c0 < len; c0 += RATE) {
+    if (live && g < RATE && c0 + g < len) s = elem(c0 + g);
+    s = pair_permute(s, q, rc, circ_rows);
+  }
+  return s;
+}
+
 }  // namespace pos
 }  // namespace v3db

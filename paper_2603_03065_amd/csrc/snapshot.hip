@@ -59,30 +59,30 @@ __global__ void __launch_bounds__(LEAF_THREADS)
   store_digests_mf(S, L, base, n_rec, digests);
 }
 
-// hash_i = Hash(i, mu_i[0..D-1], root_i), 16 lanes per list.
-__global__ void __launch_bounds__(WIDE_THREADS)
+// hash_i = Hash(i, mu_i[0..D-1], root_i), 32 lanes per list (few lists: latency-bound).
+__global__ void __launch_bounds__(PAIR_THREADS)
     k_snap_centroid(const uint64_t *__restrict__ centroids, uint32_t dim, const uint64_t *__restrict__ roots,
                     uint64_t n_list, uint64_t *__restrict__ hashes, const uint64_t *__restrict__ rc,
                     const uint32_t *__restrict__ circ_rows) {
-  const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
-  const uint64_t i = uint64_t(blockIdx.x) * WIDE_PER_BLOCK + grp;
+  const int q = threadIdx.x % PAIR_GROUP, grp = threadIdx.x / PAIR_GROUP;
+  const uint64_t i = uint64_t(blockIdx.x) * PAIR_PER_BLOCK + grp;
   const bool live = i < n_list;
   const uint64_t *mu = centroids + i * dim;
   const uint64_t *root = roots + i * DIGEST;
   auto elem = [&](uint64_t x) -> uint64_t { return x == 0 ? i : x <= dim ? mu[x - 1] : root[x - 1 - dim]; };
-  const uint64_t s = wide_sponge(1 + uint64_t(dim) + DIGEST, live, elem, g, rc, circ_rows);
-  if (live && g < DIGEST) hashes[i * DIGEST + g] = gl::canon(s);
+  const uint64_t s = pair_sponge(1 + uint64_t(dim) + DIGEST, live, elem, q, rc, circ_rows);
+  if (live && q < DIGEST) hashes[i * DIGEST + q] = gl::canon(s);
 }
 
-// root_cb = Hash(codebooks, canonical flattening of len words): one group.
-__global__ void __launch_bounds__(WIDE_THREADS)
+// root_cb = Hash(codebooks, canonical flattening of len words): one group of 32 lanes.
+__global__ void __launch_bounds__(PAIR_THREADS)
     k_snap_codebook(const uint64_t *__restrict__ codebooks, uint64_t len, uint64_t *__restrict__ root_cb,
                     const uint64_t *__restrict__ rc, const uint32_t *__restrict__ circ_rows) {
-  const int g = threadIdx.x % WIDE_GROUP, grp = threadIdx.x / WIDE_GROUP;
+  const int q = threadIdx.x % PAIR_GROUP, grp = threadIdx.x / PAIR_GROUP;
   const bool live = grp == 0;
   auto elem = [&](uint64_t x) -> uint64_t { return codebooks[x]; };
-  const uint64_t s = wide_sponge(len, live, elem, g, rc, circ_rows);
-  if (live && g < DIGEST) root_cb[g] = gl::canon(s);
+  const uint64_t s = pair_sponge(len, live, elem, q, rc, circ_rows);
+  if (live && q < DIGEST) root_cb[q] = gl::canon(s);
 }
 
 }  // namespace
@@ -112,7 +112,7 @@ v3db_status enqueue_snapshot(v3db_ctx *ctx, uint32_t log_lists, uint32_t log_slo
   hipError_t e = hipEventRecord(ctx->fork_ev, stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side_stream, ctx->fork_ev, 0);
   if (e != hipSuccess) return hip_check(e, "snapshot fork");
-  hipLaunchKernelGGL(k_snap_codebook, dim3(1), dim3(WIDE_THREADS), 0, ctx->side_stream, codebooks,
+  hipLaunchKernelGGL(k_snap_codebook, dim3(1), dim3(PAIR_THREADS), 0, ctx->side_stream, codebooks,
                      uint64_t(k) * dim, root_cb, ctx->d_pos, ctx->d_circ_rows);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipEventRecord(ctx->join_ev, ctx->side_stream);
@@ -128,8 +128,8 @@ v3db_status enqueue_snapshot(v3db_ctx *ctx, uint32_t log_lists, uint32_t log_slo
   // list roots = the level of the record tree at height log2(n_list)
   if (st == V3DB_OK) st = enqueue_merkle_levels(ctx, tree, log_lists + log_slots, log_lists, list_roots, stream);
   if (st == V3DB_OK) {
-    hipLaunchKernelGGL(k_snap_centroid, dim3((unsigned)((n_list + WIDE_PER_BLOCK - 1) / WIDE_PER_BLOCK)),
-                       dim3(WIDE_THREADS), 0, stream, centroids, dim, list_roots, n_list, top, ctx->d_pos,
+    hipLaunchKernelGGL(k_snap_centroid, dim3((unsigned)((n_list + PAIR_PER_BLOCK - 1) / PAIR_PER_BLOCK)),
+                       dim3(PAIR_THREADS), 0, stream, centroids, dim, list_roots, n_list, top, ctx->d_pos,
                        ctx->d_circ_rows);
     st = hip_check(hipGetLastError(), "snapshot centroid digests");
   }

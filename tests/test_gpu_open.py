@@ -150,3 +150,23 @@ def test_fullsize_openings_80x2p18(v3db, ctx, oracle_mod, poseidon):
         node, ci = poseidon.merkle_open(poseidon.sponge_state(vals[:, q])[:4], k, paths[q])
         assert ci == k >> (logN - h) and np.array_equal(node, cap[ci]), f"path {k}"
     assert ok == [1] * len(idx)
+
+
+def test_many_queries_use_the_16_lane_check(v3db, ctx, poseidon):
+    """More than 2^11 queries run the 16-lanes-per-query check (fewer run 32 lanes per
+    query): every honest opening accepted, tampered ones rejected, as with few."""
+    C, L, b, h = 10, 7, 3, 2
+    tr = inputs.trace(25, 0, C, L)
+    N = 1 << (L + b)
+    job = _commit(v3db, ctx, tr, b, 0, h)
+    idx = _indices(N, 3000, 7)
+    rows, paths = ctx.open_batch(job.lde, job.tree, h, v3db.to_device(idx))
+    rows, paths = _host(v3db, rows), _host(v3db, paths)
+    r, pth = rows.copy(), paths.copy()
+    bad = [5, 777, 2048, 2999]
+    for q in bad[:2]:
+        r[q, q % C] = (int(r[q, q % C]) + 1) % P
+    for q in bad[2:]:
+        pth[q, q % (L + b - h), 1] = (int(pth[q, q % (L + b - h), 1]) + 3) % P
+    ok = _ok(ctx.verify_batch(v3db.to_device(r), v3db.to_device(pth), v3db.to_device(idx), job.cap, L + b, h))
+    assert [i for i, v in enumerate(ok) if not v] == bad
