@@ -125,6 +125,9 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
         B[3] = 0;
         D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A, B, (mf_v16i){}, 0, 0, 0);
       }
+      // both products issued before either is read: the second runs on the matrix
+      // core while the first one's results are recombined
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < 2; u++)
 #pragma unroll
