@@ -97,8 +97,8 @@ __device__ __forceinline__ uint32_t sel(uint64_t m, uint32_t if0) {  // m ? IF1 
 // with three selects after two scalar mask operations.
 __device__ __forceinline__ uint64_t fix_eps(uint32_t d0, uint32_t d1, uint64_t up, uint64_t down) {
   const uint64_t pos = up & ~down, neg = down & ~up;
-  const uint32_t f0 = sel<-1>(pos, sel0<1>(neg));
   const uint32_t f1 = sel0<-1>(neg);
+  const uint32_t f0 = sel<-1>(pos, 0u - f1);  // neg: 1 = -(2^32 - 1) mod 2^32, from a plain subtraction
   uint64_t r;  // one 64-bit add (the compiler would add the high word separately)
   asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"((((uint64_t)d1) << 32) | d0), "v"((((uint64_t)f1) << 32) | f0));
   return r;
