@@ -379,11 +379,6 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
         hip_check(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "batch capture stream");
     if (st != V3DB_OK) return st;
   }
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipFuncSetAttribute((const void *)k_batch_pass, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_done = true;
-  }
   const BJob *d_jobs = (const BJob *)bg->d_table;
   const BRange *d_ranges = (const BRange *)((uint8_t *)bg->d_table + bg->jobs_bytes);
   hipStream_t cs = ctx->capture_stream;
@@ -507,6 +502,13 @@ v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs
 }
 
 }  // namespace
+
+// The batched LDE passes use the same 8192-word tiles as the single-trace ones.
+v3db_status set_batch_kernel_attributes() {
+  return hip_check(hipFuncSetAttribute((const void *)k_batch_pass, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024),
+                   "batch kernel LDS limit");
+}
 
 }  // namespace v3db
 

@@ -201,7 +201,7 @@ GL_HD uint64_t add(uint64_t a, uint64_t b) {  // a, b canonical
   // a + b < 2p: subtract p (add 2^64 - p = EPS modulo 2^64) when the sum carried
   // out of 64 bits or is at least p; written without branches
   const uint64_t s = a + b, t = s + EPS;
-  return (s < a) | (s >= P) ? t : s;
+  return ((s < a) | (s >= P)) ? t : s;
 }
 
 GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical

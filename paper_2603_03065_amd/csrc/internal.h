@@ -135,6 +135,9 @@ bool build_mf_table(const PoseidonTables &t, uint64_t out[MF_TABLE_WORDS]);
 
 // Tables (ntt.hip).
 v3db_status build_twiddles(v3db_ctx *ctx);
+// raise the LDS limit of the tiled LDE kernels on the current device (context creation)
+v3db_status set_lde_kernel_attributes();
+v3db_status set_batch_kernel_attributes();
 void free_twiddles(v3db_ctx *ctx);
 v3db_status get_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blowup, uint64_t shift, const LdePlan **out);
 

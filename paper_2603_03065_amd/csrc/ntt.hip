@@ -219,14 +219,16 @@ size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup
   return y + size_t(chunk) * (size_t(8) << (log_rows + log_blowup));
 }
 
-void lde_set_attributes() {
-  static bool done = false;
-  if (done) return;
+// Tiles above 64 KiB of LDS need the kernels' dynamic LDS limit raised to the CU's
+// 160 KiB; set on the current device when a context is created.
+v3db_status set_lde_kernel_attributes() {
   const int maxsh = 160 * 1024;
-  hipFuncSetAttribute((const void *)k_lde_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
-  hipFuncSetAttribute((const void *)k_lde_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
-  hipFuncSetAttribute((const void *)k_lde_pass3, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh);
-  done = true;
+  for (const void *k : {(const void *)k_lde_pass1, (const void *)k_lde_pass2, (const void *)k_lde_pass3}) {
+    const v3db_status st =
+        hip_check(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh), "LDE kernel LDS limit");
+    if (st != V3DB_OK) return st;
+  }
+  return V3DB_OK;
 }
 
 LdeTask lde_task(const LdePlan &plan, const uint64_t *trace, uint64_t *y, uint64_t *z, uint64_t *lde,
@@ -258,7 +260,6 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
   const LdePlan *plan = nullptr;
   v3db_status st = get_plan(ctx, log_rows, log_blowup, shift, &plan);
   if (st != V3DB_OK) return st;
-  lde_set_attributes();
   uint64_t *y = scratch;
   uint64_t *z = scratch + (size_t(n_cols) << log_rows);
   const LdeTask s = lde_task(*plan, trace, y, z, lde, layout);
