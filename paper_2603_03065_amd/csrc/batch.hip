@@ -50,7 +50,7 @@ __device__ __forceinline__ int find_range(const BRange *__restrict__ r, int n, u
   return lo;
 }
 
-__global__ void __launch_bounds__(lde::LDE_THREADS) k_batch_pass(const BJob *__restrict__ jobs,
+__global__ void __launch_bounds__(lde::LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_batch_pass(const BJob *__restrict__ jobs,
                                                                   const BRange *__restrict__ ranges, int n_ranges,
                                                                   int pass, Twiddles tw) {
   extern __shared__ uint64_t sh[];

@@ -39,6 +39,29 @@ __device__ __forceinline__ uint32_t brev(uint32_t x, int bits) {
   return bits ? (__brev(x) >> (32 - bits)) : 0u;
 }
 
+// Global-to-LDS copy of a tile of `total` <= TILE_ELEMS words (element e read by
+// src(e), stored by dst(e, v)) by a block of LDE_THREADS threads: each thread first
+// requests all its words, then stores them, so a wave keeps every load in flight at
+// once rather than waiting for each before issuing the next. Every input tile the
+// plans make fits (passes 1 and 3: T * n1 <= 8192; pass 2: T * n2 <= 8192).
+template <class Src, class Dst>
+__device__ __forceinline__ void stage_tile(int total, Src src, Dst dst) {
+  uint64_t v[MAX_PER_THREAD];
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * LDE_THREADS;
+    if (e < total) v[m] = src(e);
+  }
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    const int e = threadIdx.x + m * LDE_THREADS;
+    if (e < total) dst(e, v[m]);
+  }
+}
+
+// Elements per thread whose table loads an output loop issues before using any.
+constexpr int OUT_BATCH = 8;
+
 // Position of word w of a tile row in LDS. Rows are 2^k words; the XOR of two
 // right shifts is an invertible linear map on k-bit indices, chosen so that the
 // access patterns of the passes (runs of consecutive words, the strided words
@@ -112,15 +135,14 @@ constexpr int BFLY_ROWS = (1 << (DFT_LOG_MAX - 2)) - 1;  // rows for logS = 3..1
 // butterfly takes the R words i + j*2^logS/R, transforms them, and multiplies
 // output slot j (frequency bitrev(j)) by w_S^(i * bitrev(j)) (radix 8 with
 // logS > 3 only: for the other passes i is always 0).
-template <int R, bool INV>
+template <int R, bool INV, bool TW>
 __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, int logS,
                                          const uint64_t *__restrict__ bfly) {
   constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
   const int logStride = logS - LR;
   const int per_row = 1 << (logM - LR);
   const int nb = T * per_row;
-  const bool twiddled = R == 8 && logS > 3;
-  const uint64_t *rows = bfly + 8 * bfly_row0(R == 8 ? (logS > 3 ? logS : 3) : 3);
+  const uint64_t *rows = bfly + 8 * bfly_row0(TW ? logS : 3);
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int t = b >> (logM - LR);
     const int q = b & (per_row - 1);
@@ -132,15 +154,19 @@ __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, 
     uint64_t v[R];
 #pragma unroll
     for (int j = 0; j < R; j++) v[j] = row[wb ^ swz(j << logStride)];
-    reg_dif<R, INV>(v);
-    if (twiddled) {
+    // the twiddle row is requested together with the inputs, so its latency overlaps
+    // the butterfly instead of following it
+    uint64_t tw[8];
+    if (TW) {
       const ulonglong2 *trow = reinterpret_cast<const ulonglong2 *>(rows + 8 * i);
-      uint64_t tw[8];
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const ulonglong2 x = trow[k];
         tw[2 * k] = x.x, tw[2 * k + 1] = x.y;
       }
+    }
+    reg_dif<R, INV>(v);
+    if (TW) {
 #pragma unroll
       for (int j = 1; j < R; j++) v[j] = gl::mul(v[j], tw[j]);
     }
@@ -157,14 +183,15 @@ template <bool INV>
 __device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ bfly) {
   int logS = logS0;
   for (; logS >= 3; logS -= 3) {
-    dif_pass<8, INV>(sh, T, logM, rs, logS, bfly);
+    if (logS > 3) dif_pass<8, INV, true>(sh, T, logM, rs, logS, bfly);
+    else dif_pass<8, INV, false>(sh, T, logM, rs, logS, bfly);
     __syncthreads();
   }
   if (logS == 2) {
-    dif_pass<4, INV>(sh, T, logM, rs, 2, bfly);
+    dif_pass<4, INV, false>(sh, T, logM, rs, 2, bfly);
     __syncthreads();
   } else if (logS == 1) {
-    dif_pass<2, INV>(sh, T, logM, rs, 1, bfly);
+    dif_pass<2, INV, false>(sh, T, logM, rs, 1, bfly);
     __syncthreads();
   }
 }
@@ -205,20 +232,63 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
   uint64_t *y = s.y + size_t(col) * n;
   const int j2_0 = tile << s.logT1;
   const int total = T * n1;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int t = e & (T - 1), j1 = e >> s.logT1;
-    sh[t * rs + swz(j1)] = a[size_t(j1) * n2 + j2_0 + t];
-  }
+  stage_tile(
+      total, [&](int e) { return a[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))]; },
+      [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT1)] = v; });
   __syncthreads();
   dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv);
   const int shl = TW_LOG - s.L;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int t = e & (T - 1), k1 = e >> s.logT1;
-    const uint32_t j2 = j2_0 + t;
-    uint64_t v = sh[t * rs + swz(brev(k1, s.L1))];
-    const uint32_t ex = (uint32_t)((uint64_t(j2) * k1) & (n - 1));
-    if (ex) v = gl::mul(v, tw_pow(tw.inv_lo, tw.inv_hi, ex << shl));
-    y[size_t(k1) * n2 + j2] = v;
+  constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
+  for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
+    // w_n^(-j2 k1) = hi[x >> TW_HALF] * lo[x & lo_mask] with x = (j2 k1 mod n) << shl.
+    // Every lane requests the table words of all its elements before the first product
+    // (lanes past the end read the last element instead and store nothing), and every
+    // product is formed unconditionally, so no load is left outstanding on any path.
+    uint64_t r[OUT_BATCH];
+#pragma unroll
+    for (int u = 0; u < OUT_BATCH; u++) {
+      const int e = min(e0 + u * LDE_THREADS, total - 1);
+      const int t = e & (T - 1), k1 = e >> s.logT1;
+      const uint32_t ex = (uint32_t)((uint64_t(j2_0 + t) * k1) & (n - 1));
+      const uint32_t x = ex << shl;
+      const uint64_t v = sh[t * rs + swz(brev(k1, s.L1))];
+      const uint64_t w = gl::mul(tw.inv_hi[x >> TW_HALF], tw.inv_lo[x & lo_mask]);
+      r[u] = ex ? gl::mul(v, w) : v;
+    }
+#pragma unroll
+    for (int u = 0; u < OUT_BATCH; u++) {
+      const int e = e0 + u * LDE_THREADS;
+      if (e < total) y[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))] = r[u];
+    }
+  }
+}
+
+// Pass 2's expansion of a residue sequence to the B = 2^b cosets: input i (element e of
+// the tile, row t) times twist[r][i] lands in coset r = bitrev_b(j) at slot j of the
+// first zero-padded radix-B butterfly. The B table words of an input are requested
+// together; inputs past the end read the last one and store nothing.
+template <int B>
+__device__ __forceinline__ void twist_stage(const LdeTask &s, uint64_t *sh, int rs, int n_in, int total_in,
+                                            const uint64_t c[MAX_PER_THREAD]) {
+  const int n2 = 1 << s.L2;
+#pragma unroll
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    if (m < n_in) {
+      const int e0 = threadIdx.x + m * LDE_THREADS;
+      const int e = min(e0, total_in - 1);
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      uint64_t tv[B];
+#pragma unroll
+      for (int j = 0; j < B; j++) tv[j] = s.twist[(brev(j, s.b) << s.L2) + i];
+      uint64_t r[B];
+#pragma unroll
+      for (int j = 0; j < B; j++) r[j] = gl::mul(c[m], tv[j]);
+      if (e0 < total_in) {
+        const int wi = swz(i);
+#pragma unroll
+        for (int j = 0; j < B; j++) sh[t * rs + (wi ^ swz(j << s.L2))] = r[j];
+      }
+    }
   }
 }
 
@@ -231,7 +301,7 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
 // B cosets together; row k1 of Z gets Z[k1][e] = w_N^(k1 e) * (result at e).
 __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
                                                int tile) {
-  const int n2 = 1 << s.L2, T = 1 << s.logT2, B = 1 << s.b;
+  const int n2 = 1 << s.L2, T = 1 << s.logT2;
   const int LW = s.L2 + s.b, W = 1 << LW, rs = W + 1;
   const size_t n = size_t(1) << s.L, N = size_t(1) << (s.L + s.b);
   const int logN = s.L + s.b;
@@ -239,47 +309,72 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
   uint64_t *zc = s.z + size_t(zcol) * s.zstride;
   const int k1_0 = tile << s.logT2;
   const int total_in = T << s.L2;
-  for (int e = threadIdx.x; e < total_in; e += blockDim.x) {
-    const int t = e >> s.L2, j = e & (n2 - 1);
-    sh[t * rs + swz(j)] = y[size_t(k1_0 + t) * n2 + j];
-  }
+  stage_tile(
+      total_in, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
+      [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
   __syncthreads();
   dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
+  // this thread's inputs m < n_in (the same count for the whole block): n^-1 s^k1 c'
+  const int n_in = (total_in + LDE_THREADS - 1) / LDE_THREADS;
   uint64_t c[MAX_PER_THREAD];
 #pragma unroll
   for (int m = 0; m < MAX_PER_THREAD; m++) {
-    const int e = threadIdx.x + m * LDE_THREADS;
-    if (e < total_in) {
+    if (m < n_in) {
+      const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
       const int t = e >> s.L2, i = e & (n2 - 1);
       c[m] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MAX_PER_THREAD; m++) {
-    const int e = threadIdx.x + m * LDE_THREADS;
-    if (e < total_in) {
-      const int t = e >> s.L2, i = e & (n2 - 1);
-      const int wi = swz(i);
-      for (int j = 0; j < B; j++) sh[t * rs + (wi ^ swz(j << s.L2))] = gl::mul(c[m], s.twist[(brev(j, s.b) << s.L2) + i]);
-    }
+  switch (s.b) {
+    case 0: twist_stage<1>(s, sh, rs, n_in, total_in, c); break;
+    case 1: twist_stage<2>(s, sh, rs, n_in, total_in, c); break;
+    case 2: twist_stage<4>(s, sh, rs, n_in, total_in, c); break;
+    case 3: twist_stage<8>(s, sh, rs, n_in, total_in, c); break;
+    default: twist_stage<16>(s, sh, rs, n_in, total_in, c); break;
   }
   __syncthreads();
   dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd);
   const int total_out = T << LW;
   const int shl = TW_LOG - logN;
-  for (int e = threadIdx.x; e < total_out; e += blockDim.x) {
-    const int t = e >> LW, f = e & (W - 1);
-    const uint32_t k1 = k1_0 + t;
-    uint64_t v = sh[t * rs + swz(brev(f, LW))];
-    const size_t zi = (size_t(k1) << LW) + f;
-    if (s.ztw) {
-      v = gl::mul(v, s.ztw[zi]);
-    } else {
-      const uint32_t ex = (uint32_t)((uint64_t(k1) * f) & (N - 1));
-      if (ex) v = gl::mul(v, tw_pow(tw.fwd_lo, tw.fwd_hi, ex << shl));
+  constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
+  // w_N^(k1 e) for each element (one ztw word, or two words of the two-level table),
+  // requested for a batch of elements before the first product; lanes past the end read
+  // the last element and store nothing, and every product is formed unconditionally
+  if (s.ztw) {
+    for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
+      uint64_t r[OUT_BATCH];
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH; u++) {
+        const int e = min(e0 + u * LDE_THREADS, total_out - 1);
+        const int t = e >> LW, f = e & (W - 1);
+        r[u] = gl::mul(sh[t * rs + swz(brev(f, LW))], s.ztw[(size_t(k1_0 + t) << LW) + f]);
+      }
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH; u++) {
+        const int e = e0 + u * LDE_THREADS;
+        if (e < total_out) zc[(size_t(k1_0 + (e >> LW)) << LW) + (e & (W - 1))] = r[u];
+      }
     }
-    zc[zi] = v;
+  } else {
+    for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
+      uint64_t r[OUT_BATCH];
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH; u++) {
+        const int e = min(e0 + u * LDE_THREADS, total_out - 1);
+        const int t = e >> LW, f = e & (W - 1);
+        const uint32_t ex = (uint32_t)((uint64_t(k1_0 + t) * f) & (N - 1));
+        const uint32_t x = ex << shl;
+        const uint64_t v = sh[t * rs + swz(brev(f, LW))];
+        const uint64_t w = gl::mul(tw.fwd_hi[x >> TW_HALF], tw.fwd_lo[x & lo_mask]);
+        r[u] = ex ? gl::mul(v, w) : v;
+      }
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH; u++) {
+        const int e = e0 + u * LDE_THREADS;
+        if (e < total_out) zc[(size_t(k1_0 + (e >> LW)) << LW) + (e & (W - 1))] = r[u];
+      }
+    }
   }
 }
 
@@ -295,10 +390,9 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
   uint64_t *out = s.lde + size_t(col) * N;
   const int e0 = tile << s.logT3;
   const int total = T * n1;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int t = e & (T - 1), k1 = e >> s.logT3;
-    sh[t * rs + swz(k1)] = zc[(size_t(k1) << LW) + e0 + t];
-  }
+  stage_tile(
+      total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
+      [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT3)] = v; });
   __syncthreads();
   dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd);
   if (!s.bitrev) {

@@ -8,18 +8,18 @@ namespace {
 
 using namespace lde;
 
-__global__ void __launch_bounds__(LDE_THREADS) k_lde_pass1(LdeTask s, Twiddles tw) {
+__global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass1(LdeTask s, Twiddles tw) {
   extern __shared__ uint64_t sh[];
   lde_pass1_tile(s, tw, sh, blockIdx.y, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(LDE_THREADS) k_lde_pass2(LdeTask s, Twiddles tw, int col0) {
+__global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass2(LdeTask s, Twiddles tw, int col0) {
   extern __shared__ uint64_t sh[];
   const int col = col0 + blockIdx.y;
   lde_pass2_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(LDE_THREADS) k_lde_pass3(LdeTask s, Twiddles tw, int col0) {
+__global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass3(LdeTask s, Twiddles tw, int col0) {
   extern __shared__ uint64_t sh[];
   const int col = col0 + blockIdx.y;
   lde_pass3_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
