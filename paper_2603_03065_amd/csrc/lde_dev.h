@@ -180,7 +180,7 @@ __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, 
 // Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
 // were done another way).
 template <bool INV>
-__device__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ bfly) {
+__device__ __forceinline__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ bfly) {
   int logS = logS0;
   for (; logS >= 3; logS -= 3) {
     if (logS > 3) dif_pass<8, INV, true>(sh, T, logM, rs, logS, bfly);
