@@ -49,16 +49,36 @@ __global__ void __launch_bounds__(GP_THREADS)
                  uint64_t *__restrict__ z, uint64_t *__restrict__ partials) {
   __shared__ uint64_t sh[GP_THREADS];
   const uint64_t base = uint64_t(blockIdx.x) * GP_TILE;
+  // Horner over the columns, highest first, for 8 of the thread's 16 rows at a time:
+  // each column's 8 words are requested together (rows past the end read row n - 1 and
+  // are dropped below), so the loads of a column overlap instead of following one another
+  constexpr int G = 8;
   uint64_t prod = 1;
-#pragma unroll 4
-  for (int k = 0; k < GP_PER_THREAD; k++) {
-    const uint64_t i = base + uint64_t(k) * GP_THREADS + threadIdx.x;
-    if (i < n) {
-      uint64_t c = cols[uint64_t(width - 1) * n + i];
-      for (int w = (int)width - 2; w >= 0; w--) c = gl::add(gl::mul(c, beta), cols[uint64_t(w) * n + i]);
-      const uint64_t d = gl::sub(alpha, c);
-      if (z) z[i] = d;
-      prod = gl::mul(prod, d);
+  for (int g = 0; g < GP_PER_THREAD; g += G) {
+    uint64_t c[G];
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+      const uint64_t i = base + uint64_t(g + k) * GP_THREADS + threadIdx.x;
+      c[k] = cols[uint64_t(width - 1) * n + (i < n ? i : n - 1)];
+    }
+    for (int w = (int)width - 2; w >= 0; w--) {
+      uint64_t x[G];
+#pragma unroll
+      for (int k = 0; k < G; k++) {
+        const uint64_t i = base + uint64_t(g + k) * GP_THREADS + threadIdx.x;
+        x[k] = cols[uint64_t(w) * n + (i < n ? i : n - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < G; k++) c[k] = gl::add(gl::mul(c[k], beta), x[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+      const uint64_t i = base + uint64_t(g + k) * GP_THREADS + threadIdx.x;
+      if (i < n) {
+        const uint64_t d = gl::sub(alpha, c[k]);
+        if (z) z[i] = d;
+        prod = gl::mul(prod, d);
+      }
     }
   }
   const uint64_t p = block_product(prod, sh);
@@ -91,10 +111,20 @@ __global__ void __launch_bounds__(GP_THREADS)
   __shared__ uint64_t sh[2 * GP_THREADS];
   const uint64_t base = uint64_t(blockIdx.x) * GP_TILE;
   auto pos = [](int w) { return w + (w >> 4); };
-  for (int k = 0; k < GP_PER_THREAD; k++) {
-    const int w = k * GP_THREADS + threadIdx.x;
-    const uint64_t i = base + w;
-    tile[pos(w)] = i < n ? z[i] : 1;
+  {
+    // all 16 words requested before any is stored (rows past the end read row n - 1
+    // and store 1)
+    uint64_t x[GP_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < GP_PER_THREAD; k++) {
+      const uint64_t i = base + k * GP_THREADS + threadIdx.x;
+      x[k] = z[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < GP_PER_THREAD; k++) {
+      const int w = k * GP_THREADS + threadIdx.x;
+      tile[pos(w)] = base + w < n ? x[k] : 1;
+    }
   }
   __syncthreads();
   const int w0 = threadIdx.x * GP_PER_THREAD;
