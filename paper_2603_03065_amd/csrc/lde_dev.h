@@ -217,11 +217,13 @@ struct LdeTask {
   uint64_t zstride;
   int L, b, L1, L2;       // log n, log blowup, log n1, log n2 (n = n1 n2)
   int logT1, logT2, logT3;
+  int logT2i;             // log2 rows per tile of the separate inverse part of pass 2
   int bitrev;
 };
 
 __device__ __forceinline__ int lde_tiles1(const LdeTask &t) { return (1 << t.L2) >> t.logT1; }
 __device__ __forceinline__ int lde_tiles2(const LdeTask &t) { return (1 << t.L1) >> t.logT2; }
+__device__ __forceinline__ int lde_tiles2i(const LdeTask &t) { return (1 << t.L1) >> t.logT2i; }
 __device__ __forceinline__ int lde_tiles3(const LdeTask &t) { return (1 << (t.L2 + t.b)) >> t.logT3; }
 
 // Pass 1, tile = T consecutive j2 of column col.
@@ -293,12 +295,48 @@ __device__ __forceinline__ void twist_stage(const LdeTask &s, uint64_t *sh, int 
 }
 
 // Pass 2, tile = T consecutive residues k1 (rows of Y) of column col; W = B*n2.
+// Pass 2's inverse part on its own, tile = T2i consecutive rows k1 of Y (column col):
+// row k1 is transformed back, giving n*c[k1 + n1*k2] in bit-reversed positions, and
+// written over itself in natural order k2, times n^-1 s^k1. A tile holds up to 8192
+// words, so every thread has butterflies (inside pass 2 a tile has only the T2 rows
+// its W-point outputs leave room for: T2*n2 = 8192/B inputs).
+__device__ __forceinline__ void lde_pass2i_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col,
+                                                int tile) {
+  const int n2 = 1 << s.L2, T = 1 << s.logT2i, rs = n2 + 1;
+  const size_t n = size_t(1) << s.L;
+  uint64_t *y = s.y + size_t(col) * n;
+  const int k1_0 = tile << s.logT2i;
+  const int total = T << s.L2;
+  stage_tile(
+      total, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
+      [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
+  __syncthreads();
+  dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
+  for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
+    uint64_t r[OUT_BATCH];
+#pragma unroll
+    for (int u = 0; u < OUT_BATCH; u++) {
+      const int e = min(e0 + u * LDE_THREADS, total - 1);
+      const int t = e >> s.L2, i = e & (n2 - 1);
+      r[u] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
+    }
+#pragma unroll
+    for (int u = 0; u < OUT_BATCH; u++) {
+      const int e = e0 + u * LDE_THREADS;
+      if (e < total) y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))] = r[u];
+    }
+  }
+}
+
+// Pass 2, tile = T consecutive residues k1 (rows of Y) of column col; W = B*n2.
 // Row k1 of Y is transformed back (giving n*c[k1 + n1*k2] in bit-reversed
 // positions), scaled by n^-1 s^k1 and expanded to the W-point zero-padded
 // transform: its first radix-B decimation-in-frequency pass has a single
 // nonzero input per butterfly, so output slot j of butterfly i is the input
 // times the twist (s^n1 w_W^r)^i, r = bitrev(j). The remaining passes run on the
 // B cosets together; row k1 of Z gets Z[k1][e] = w_N^(k1 e) * (result at e).
+// PRE: the rows of Y already hold n^-1 s^k1 c' in natural order (lde_pass2i_tile).
+template <bool PRE>
 __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
                                                int tile) {
   const int n2 = 1 << s.L2, T = 1 << s.logT2;
@@ -309,23 +347,33 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
   uint64_t *zc = s.z + size_t(zcol) * s.zstride;
   const int k1_0 = tile << s.logT2;
   const int total_in = T << s.L2;
-  stage_tile(
-      total_in, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
-      [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
-  __syncthreads();
-  dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
   // this thread's inputs m < n_in (the same count for the whole block): n^-1 s^k1 c'
   const int n_in = (total_in + LDE_THREADS - 1) / LDE_THREADS;
   uint64_t c[MAX_PER_THREAD];
+  if (PRE) {
 #pragma unroll
-  for (int m = 0; m < MAX_PER_THREAD; m++) {
-    if (m < n_in) {
-      const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
-      const int t = e >> s.L2, i = e & (n2 - 1);
-      c[m] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
+    for (int m = 0; m < MAX_PER_THREAD; m++) {
+      if (m < n_in) {
+        const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
+        c[m] = y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))];
+      }
     }
+  } else {
+    stage_tile(
+        total_in, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
+        [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
+    __syncthreads();
+    dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
+#pragma unroll
+    for (int m = 0; m < MAX_PER_THREAD; m++) {
+      if (m < n_in) {
+        const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
+        const int t = e >> s.L2, i = e & (n2 - 1);
+        c[m] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   switch (s.b) {
     case 0: twist_stage<1>(s, sh, rs, n_in, total_in, c); break;
     case 1: twist_stage<2>(s, sh, rs, n_in, total_in, c); break;
@@ -420,6 +468,7 @@ namespace lde {
 // LDS words a pass needs for its tile.
 __host__ __device__ inline size_t lde_lds_words(int pass, int L1, int L2, int b, int logT) {
   if (pass == 2) return (size_t(1) << logT) * ((size_t(1) << (L2 + b)) + 1);
+  if (pass == 4) return (size_t(1) << logT) * ((size_t(1) << L2) + 1);  // pass 2's inverse part
   return (size_t(1) << logT) * ((size_t(1) << L1) + 1);
 }
 

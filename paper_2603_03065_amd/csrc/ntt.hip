@@ -13,10 +13,15 @@ __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_e
   lde_pass1_tile(s, tw, sh, blockIdx.y, blockIdx.x);
 }
 
+__global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass2i(LdeTask s, Twiddles tw) {
+  extern __shared__ uint64_t sh[];
+  lde_pass2i_tile(s, tw, sh, blockIdx.y, blockIdx.x);
+}
+
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass2(LdeTask s, Twiddles tw, int col0) {
   extern __shared__ uint64_t sh[];
   const int col = col0 + blockIdx.y;
-  lde_pass2_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
+  lde_pass2_tile<true>(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass3(LdeTask s, Twiddles tw, int col0) {
@@ -126,6 +131,7 @@ static v3db_status build_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blo
   p.logT1 = tile_log(p.L1, p.L2, sched.cap1);
   p.logT2 = tile_log(p.L2 + log_blowup, p.L1, sched.cap2);
   p.logT3 = tile_log(p.L1, p.L2 + log_blowup, sched.cap3);
+  p.logT2i = tile_log(p.L2, p.L1, 4);
   p.chunk = sched.chunk;
   const size_t n1 = size_t(1) << p.L1, n2 = size_t(1) << p.L2, B = size_t(1) << log_blowup;
   std::vector<uint64_t> host(B * n2 + n1);
@@ -223,7 +229,8 @@ size_t lde_scratch_bytes(uint32_t n_cols, uint32_t log_rows, uint32_t log_blowup
 // 160 KiB; set on the current device when a context is created.
 v3db_status set_lde_kernel_attributes() {
   const int maxsh = 160 * 1024;
-  for (const void *k : {(const void *)k_lde_pass1, (const void *)k_lde_pass2, (const void *)k_lde_pass3}) {
+  for (const void *k : {(const void *)k_lde_pass1, (const void *)k_lde_pass2i, (const void *)k_lde_pass2,
+                        (const void *)k_lde_pass3}) {
     const v3db_status st =
         hip_check(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, maxsh), "LDE kernel LDS limit");
     if (st != V3DB_OK) return st;
@@ -247,6 +254,7 @@ LdeTask lde_task(const LdePlan &plan, const uint64_t *trace, uint64_t *y, uint64
   s.logT1 = (int)plan.logT1;
   s.logT2 = (int)plan.logT2;
   s.logT3 = (int)plan.logT3;
+  s.logT2i = (int)plan.logT2i;
   s.bitrev = layout == V3DB_LAYOUT_BITREV;
   const size_t N = size_t(1) << (s.L + s.b);
   s.z = s.bitrev ? z : lde;
@@ -267,8 +275,11 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
   const size_t sh1 = lde_lds_words(1, s.L1, s.L2, s.b, s.logT1) * 8;
   const size_t sh2 = lde_lds_words(2, s.L1, s.L2, s.b, s.logT2) * 8;
   const size_t sh3 = lde_lds_words(3, s.L1, s.L2, s.b, s.logT3) * 8;
+  const size_t sh2i = lde_lds_words(4, s.L1, s.L2, s.b, s.logT2i) * 8;
   const unsigned t1 = (1u << s.L2) >> s.logT1, t2 = (1u << s.L1) >> s.logT2, t3 = (1u << (s.L2 + s.b)) >> s.logT3;
+  const unsigned t2i = (1u << s.L1) >> s.logT2i;
   hipLaunchKernelGGL(k_lde_pass1, dim3(t1, n_cols), dim3(LDE_THREADS), sh1, stream, s, tw);
+  hipLaunchKernelGGL(k_lde_pass2i, dim3(t2i, n_cols), dim3(LDE_THREADS), sh2i, stream, s, tw);
   // a chunk of columns at a time through passes 2 and 3, so a chunk's Z is still
   // in the Infinity Cache when pass 3 reads it
   const uint32_t chunk = n_cols < plan->chunk ? n_cols : plan->chunk;
