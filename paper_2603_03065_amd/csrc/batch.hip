@@ -26,6 +26,7 @@ namespace {
 constexpr int POS_THREADS = 256;
 constexpr int LEAF_ROWS = 256;     // rows per leaf-hashing block
 constexpr int MERKLE_NODES = 256;  // nodes per Merkle block
+constexpr int PASS_2I = 8;         // phase kind of pass 2's inverse part (k_batch_pass)
 
 // Device descriptor of one trace of a batch.
 struct BJob {
@@ -60,10 +61,13 @@ __global__ void __launch_bounds__(lde::LDE_THREADS) __attribute__((amdgpu_waves_
   if (pass == 1) {
     const int tiles = lde::lde_tiles1(t);
     lde::lde_pass1_tile(t, tw, sh, local / tiles, local % tiles);
+  } else if (pass == PASS_2I) {
+    const int tiles = lde::lde_tiles2i(t);
+    lde::lde_pass2i_tile(t, tw, sh, local / tiles, local % tiles);
   } else if (pass == 2) {
     const int tiles = lde::lde_tiles2(t);
     const int col = local / tiles;
-    lde::lde_pass2_tile<false>(t, tw, sh, col, col, local % tiles);
+    lde::lde_pass2_tile<true>(t, tw, sh, col, col, local % tiles);
   } else {
     const int tiles = lde::lde_tiles3(t);
     const int col = local / tiles;
@@ -262,7 +266,8 @@ v3db_status commit_single(v3db_ctx *ctx, const v3db_commit_job &j, void *scratch
 }
 
 struct Phase {
-  int kind;   // 1..3 LDE pass, 4 leaf hashing, 5 Merkle depth, 6 (7) Merkle depth with 16 (32) lanes per node
+  int kind;   // 1..3 LDE pass (PASS_2I: pass 2's inverse part), 4 leaf hashing, 5 Merkle depth, 6 (7) Merkle
+              // depth with 16 (32) lanes per node
   int depth;  // Merkle depth
   size_t ranges_off, n_ranges;
   uint32_t blocks;
@@ -297,8 +302,11 @@ void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3d
     lds[1] = std::max(lds[1], lde::lde_lds_words(1, L1, L2, b, p.logT1) * 8);
     lds[2] = std::max(lds[2], lde::lde_lds_words(2, L1, L2, b, p.logT2) * 8);
     lds[3] = std::max(lds[3], lde::lde_lds_words(3, L1, L2, b, p.logT3) * 8);
+    lds[0] = std::max(lds[0], lde::lde_lds_words(4, L1, L2, b, p.logT2i) * 8);
   }
   add_phase(1, 0, lds[1], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L2) >> plans[i]->logT1); });
+  add_phase(PASS_2I, 0, lds[0],
+            [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2i); });
   add_phase(2, 0, lds[2], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2); });
   add_phase(3, 0, lds[3], [&](size_t i) {
     return jobs[i].n_cols * ((1u << (plans[i]->L2 + plans[i]->log_blowup)) >> plans[i]->logT3);
@@ -389,7 +397,7 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
   for (const Phase &ph : g.phases) {
     const BRange *rr = d_ranges + ph.ranges_off;
     const int nr = (int)ph.n_ranges;
-    if (ph.kind <= 3)
+    if (ph.kind <= 3 || ph.kind == PASS_2I)
       hipLaunchKernelGGL(k_batch_pass, dim3(ph.blocks), dim3(lde::LDE_THREADS), ph.lds, cs, d_jobs, rr, nr, ph.kind,
                          tw);
     else if (ph.kind == 4 && ctx->mf)
