@@ -16,6 +16,10 @@
 // (LDE[e + B n2 m2] = sum_k1 w_n1^(k1 m2) s^k1 w_N^(k1 e) sum_k2 c[k1+n1 k2]
 //  (s^n1)^k2 w_(B n2)^(k2 e) follows from j = k1 + n1 k2 and k = e + B n2 m2.)
 //
+// Pass 2's first half (the size-n2 inverse transforms and the scaling by n^-1 s^k1)
+// runs as a kernel of its own, pass 2i, over tiles of up to 16 rows of Y, writing the
+// scaled coefficients back over Y; pass 2 proper then starts from them.
+//
 // Each pass moves tiles of T adjacent columns/rows so global accesses are runs
 // of T*8 bytes and does its sub-transforms in LDS with radix-8 register
 // butterflies (decimation in frequency: natural order in, bit-reversed out;

@@ -132,6 +132,12 @@ static v3db_status build_plan(v3db_ctx *ctx, uint32_t log_rows, uint32_t log_blo
   p.logT2 = tile_log(p.L2 + log_blowup, p.L1, sched.cap2);
   p.logT3 = tile_log(p.L1, p.L2 + log_blowup, sched.cap3);
   p.logT2i = tile_log(p.L2, p.L1, 4);
+  // the tile loaders hold one tile of input words per block in registers
+  // (MAX_PER_THREAD per thread): passes 1, 2i and 3 read T * (row length) words and
+  // pass 2 reads T * n2
+  auto fits = [](uint32_t log_words) { return (size_t(1) << log_words) <= size_t(lde::TILE_ELEMS); };
+  if (!fits(p.L1 + p.logT1) || !fits(p.L2 + p.logT2i) || !fits(p.L1 + p.logT3) || !fits(p.L2 + p.logT2))
+    return set_error(V3DB_ERR_UNSUPPORTED, "LDE plan: an input tile exceeds 8192 words");
   p.chunk = sched.chunk;
   const size_t n1 = size_t(1) << p.L1, n2 = size_t(1) << p.L2, B = size_t(1) << log_blowup;
   std::vector<uint64_t> host(B * n2 + n1);
