@@ -262,12 +262,7 @@ void v3db_ctx_destroy(v3db_ctx *ctx) {
   if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
-  for (int i = 0; i < v3db_ctx::FRI_STREAMS; i++) {
-    if (ctx->fri_streams[i]) (void)hipStreamDestroy(ctx->fri_streams[i]);
-    if (ctx->fri_done[i]) (void)hipEventDestroy(ctx->fri_done[i]);
-  }
-  for (hipEvent_t e : ctx->fri_ready)
-    if (e) (void)hipEventDestroy(e);
+  free_tree_batch(ctx);
   prof_drop(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   ctx->event_pool.clear();
@@ -643,7 +638,7 @@ v3db_status v3db_fri_commit(v3db_ctx *ctx, const uint64_t *d_codeword, uint32_t 
   v3db_status st = check_canonical(ctx, d_codeword, size_t(1) << log_n, s);
   if (st != V3DB_OK) return st;
   void *z = nullptr;
-  if (!d_trees) {  // every round's tree at once: the rounds' trees are built concurrently
+  if (!d_trees) {  // every round's tree at once: the rounds' trees are built in one batch
     st = ctx_scratch(ctx, s, fri_tree_digests(log_n, rounds, cap_height) * DIGEST * 8, &z);
     if (st != V3DB_OK) return st;
   }

@@ -279,22 +279,51 @@ struct GroupPlan {
   std::vector<Phase> phases;
 };
 
+// Phase `kind` over the jobs: job i contributes items_of(i) blocks (a range of its own).
+template <class F>
+void add_phase(GroupPlan &g, size_t nj, int kind, int depth, size_t lds, F items_of) {
+  Phase ph{kind, depth, g.ranges.size(), 0, 0, lds};
+  uint32_t first = 0;
+  for (size_t i = 0; i < nj; i++) {
+    const uint32_t cnt = items_of(i);
+    if (!cnt) continue;
+    g.ranges.push_back(BRange{first, (uint32_t)i, cnt, 0});
+    first += cnt;
+  }
+  ph.n_ranges = g.ranges.size() - ph.ranges_off;
+  ph.blocks = first;
+  if (ph.blocks) g.phases.push_back(ph);
+}
+
+// Leaf hashing and the Merkle depths of trees with 2^logN[i] leaves and cap heights
+// cap[i]: one phase per depth over every tree that still has that depth, its layout
+// (one node per lane, 16 or 32 lanes per node) chosen by the depth's total node count.
+void add_tree_phases(GroupPlan &g, const std::vector<uint32_t> &logN, const std::vector<uint32_t> &cap) {
+  const size_t nj = logN.size();
+  add_phase(g, nj, 4, 0, 0, [&](size_t i) {
+    const uint64_t rows = uint64_t(1) << logN[i];
+    return (uint32_t)((rows + LEAF_ROWS - 1) / LEAF_ROWS);
+  });
+  uint32_t max_depth = 0;
+  for (size_t i = 0; i < nj; i++) max_depth = std::max(max_depth, logN[i] - cap[i]);
+  for (uint32_t d = 1; d <= max_depth; d++) {
+    auto nodes_of = [&](size_t i) -> uint64_t {
+      if (logN[i] < d || logN[i] - d < cap[i]) return 0;
+      return uint64_t(1) << (logN[i] - d);
+    };
+    uint64_t total = 0;
+    for (size_t i = 0; i < nj; i++) total += nodes_of(i);
+    // few nodes at this depth in all: 16 or 32 lanes per node for a shorter chain
+    const bool pair = total <= MERKLE_PAIR_MAX_NODES, wide = total <= MERKLE_WIDE_MAX_NODES;
+    const uint64_t per_block = pair ? pos::PAIR_PER_BLOCK : wide ? pos::WIDE_PER_BLOCK : MERKLE_NODES;
+    add_phase(g, nj, pair ? 7 : wide ? 6 : 5, (int)d, 0,
+              [&](size_t i) -> uint32_t { return (uint32_t)((nodes_of(i) + per_block - 1) / per_block); });
+  }
+}
+
 void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3db_commit_job> &jobs,
                 GroupPlan &g) {
   const size_t nj = jobs.size();
-  auto add_phase = [&](int kind, int depth, size_t lds, auto items_of) {
-    Phase ph{kind, depth, g.ranges.size(), 0, 0, lds};
-    uint32_t first = 0;
-    for (size_t i = 0; i < nj; i++) {
-      const uint32_t cnt = items_of(i);
-      if (!cnt) continue;
-      g.ranges.push_back(BRange{first, (uint32_t)i, cnt, 0});
-      first += cnt;
-    }
-    ph.n_ranges = g.ranges.size() - ph.ranges_off;
-    ph.blocks = first;
-    if (ph.blocks) g.phases.push_back(ph);
-  };
   size_t lds[4] = {0, 0, 0, 0};
   for (size_t i = 0; i < nj; i++) {
     const LdePlan &p = *plans[i];
@@ -304,34 +333,19 @@ void plan_group(const std::vector<const LdePlan *> &plans, const std::vector<v3d
     lds[3] = std::max(lds[3], lde::lde_lds_words(3, L1, L2, b, p.logT3) * 8);
     lds[0] = std::max(lds[0], lde::lde_lds_words(4, L1, L2, b, p.logT2i) * 8);
   }
-  add_phase(1, 0, lds[1], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L2) >> plans[i]->logT1); });
-  add_phase(PASS_2I, 0, lds[0],
+  add_phase(g, nj, 1, 0, lds[1], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L2) >> plans[i]->logT1); });
+  add_phase(g, nj, PASS_2I, 0, lds[0],
             [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2i); });
-  add_phase(2, 0, lds[2], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2); });
-  add_phase(3, 0, lds[3], [&](size_t i) {
+  add_phase(g, nj, 2, 0, lds[2], [&](size_t i) { return jobs[i].n_cols * ((1u << plans[i]->L1) >> plans[i]->logT2); });
+  add_phase(g, nj, 3, 0, lds[3], [&](size_t i) {
     return jobs[i].n_cols * ((1u << (plans[i]->L2 + plans[i]->log_blowup)) >> plans[i]->logT3);
   });
-  add_phase(4, 0, 0, [&](size_t i) {
-    const uint64_t rows = uint64_t(1) << (jobs[i].log_rows + jobs[i].log_blowup);
-    return (uint32_t)((rows + LEAF_ROWS - 1) / LEAF_ROWS);
-  });
-  uint32_t max_depth = 0;
-  for (size_t i = 0; i < nj; i++)
-    max_depth = std::max(max_depth, jobs[i].log_rows + jobs[i].log_blowup - jobs[i].cap_height);
-  for (uint32_t d = 1; d <= max_depth; d++) {
-    auto nodes_of = [&](size_t i) -> uint64_t {
-      const uint32_t logN = jobs[i].log_rows + jobs[i].log_blowup;
-      if (logN < d || logN - d < jobs[i].cap_height) return 0;
-      return uint64_t(1) << (logN - d);
-    };
-    uint64_t total = 0;
-    for (size_t i = 0; i < nj; i++) total += nodes_of(i);
-    // few nodes at this depth in all: 16 lanes per node for a shorter chain
-    const bool pair = total <= MERKLE_PAIR_MAX_NODES, wide = total <= MERKLE_WIDE_MAX_NODES;
-    const uint64_t per_block = pair ? pos::PAIR_PER_BLOCK : wide ? pos::WIDE_PER_BLOCK : MERKLE_NODES;
-    add_phase(pair ? 7 : wide ? 6 : 5, (int)d, 0,
-              [&](size_t i) -> uint32_t { return (uint32_t)((nodes_of(i) + per_block - 1) / per_block); });
+  std::vector<uint32_t> logN(nj), cap(nj);
+  for (size_t i = 0; i < nj; i++) {
+    logN[i] = jobs[i].log_rows + jobs[i].log_blowup;
+    cap[i] = jobs[i].cap_height;
   }
+  add_tree_phases(g, logN, cap);
 }
 
 // Graphs are cached per stream too: a graph's table is rewritten only by calls
@@ -381,17 +395,9 @@ void free_batch_graphs(v3db_ctx *ctx) {
 
 namespace {
 
-v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
-  if (!ctx->capture_stream) {
-    v3db_status st =
-        hip_check(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "batch capture stream");
-    if (st != V3DB_OK) return st;
-  }
-  const BJob *d_jobs = (const BJob *)bg->d_table;
-  const BRange *d_ranges = (const BRange *)((uint8_t *)bg->d_table + bg->jobs_bytes);
-  hipStream_t cs = ctx->capture_stream;
-  v3db_status st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-  if (st != V3DB_OK) return st;
+// The kernels of every phase of g, in order, on stream cs; the job and range tables
+// are on the device.
+void launch_phases(v3db_ctx *ctx, const GroupPlan &g, const BJob *d_jobs, const BRange *d_ranges, hipStream_t cs) {
   const Twiddles tw = ctx->tw;
   const pos::Circ c = pos::circ_of(ctx);
   for (const Phase &ph : g.phases) {
@@ -418,6 +424,20 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
       hipLaunchKernelGGL(k_batch_merkle_wide, dim3(ph.blocks), dim3(pos::WIDE_THREADS), 0, cs, d_jobs, rr, nr,
                          ph.depth, ctx->d_pos, ctx->d_circ_rows);
   }
+}
+
+v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
+  if (!ctx->capture_stream) {
+    v3db_status st =
+        hip_check(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "batch capture stream");
+    if (st != V3DB_OK) return st;
+  }
+  const BJob *d_jobs = (const BJob *)bg->d_table;
+  const BRange *d_ranges = (const BRange *)((uint8_t *)bg->d_table + bg->jobs_bytes);
+  hipStream_t cs = ctx->capture_stream;
+  v3db_status st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (st != V3DB_OK) return st;
+  launch_phases(ctx, g, d_jobs, d_ranges, cs);
   const hipError_t le = hipGetLastError();
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
@@ -510,6 +530,79 @@ v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs
 }
 
 }  // namespace
+
+static void free_tree_batch_tables(v3db_ctx *ctx) {
+  if (ctx->tree_table_h) (void)hipHostFree(ctx->tree_table_h);
+  if (ctx->tree_table_d) ctx_free(ctx, ctx->tree_table_d, ctx->tree_table_bytes);
+  ctx->tree_table_h = ctx->tree_table_d = nullptr;
+  ctx->tree_table_bytes = 0;
+}
+
+v3db_status enqueue_tree_batch(v3db_ctx *ctx, const TreeJob *jobs, size_t n, hipStream_t s) {
+  if (n == 0) return V3DB_OK;
+  std::vector<uint32_t> logN(n), cap(n);
+  std::vector<BJob> bj(n);
+  for (size_t i = 0; i < n; i++) {
+    logN[i] = jobs[i].log_leaves;
+    cap[i] = jobs[i].cap_height;
+    BJob &b = bj[i];
+    b = BJob{};
+    b.t.lde = const_cast<uint64_t *>(jobs[i].mat);  // read only by the hashing kernels
+    b.tree = jobs[i].tree;
+    b.cap = jobs[i].cap;
+    b.n_cols = jobs[i].n_cols;
+    b.logN = jobs[i].log_leaves;
+    b.cap_height = jobs[i].cap_height;
+  }
+  GroupPlan gp;
+  add_tree_phases(gp, logN, cap);
+  const size_t jobs_bytes = (n * sizeof(BJob) + 255) & ~size_t(255);
+  const size_t bytes = jobs_bytes + gp.ranges.size() * sizeof(BRange);
+  hipError_t e = hipSuccess;
+  if (!ctx->tree_table_staged) e = hipEventCreateWithFlags(&ctx->tree_table_staged, hipEventDisableTiming);
+  if (e == hipSuccess && !ctx->tree_table_done) e = hipEventCreateWithFlags(&ctx->tree_table_done, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_check(e, "tree batch events");
+  // the last batch (possibly on another stream) may still read the device table and
+  // the staging copy: wait for its upload before rewriting the staging copy, and
+  // order this call's upload after its kernels
+  e = hipEventSynchronize(ctx->tree_table_staged);
+  if (e == hipSuccess && bytes > ctx->tree_table_bytes) {
+    e = hipEventSynchronize(ctx->tree_table_done);
+    if (e == hipSuccess) {
+      free_tree_batch_tables(ctx);
+      void *d = nullptr, *h = nullptr;
+      v3db_status st = ctx_alloc(ctx, &d, bytes, "tree batch table");
+      if (st != V3DB_OK) return st;
+      e = hipHostMalloc(&h, bytes, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        ctx_free(ctx, d, bytes);
+        return hip_check(e, "tree batch staging");
+      }
+      ctx->tree_table_d = d;
+      ctx->tree_table_h = h;
+      ctx->tree_table_bytes = bytes;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->tree_table_done, 0);
+  if (e != hipSuccess) return hip_check(e, "tree batch table");
+  memcpy(ctx->tree_table_h, bj.data(), n * sizeof(BJob));
+  memcpy((uint8_t *)ctx->tree_table_h + jobs_bytes, gp.ranges.data(), gp.ranges.size() * sizeof(BRange));
+  e = hipMemcpyAsync(ctx->tree_table_d, ctx->tree_table_h, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->tree_table_staged, s);
+  if (e != hipSuccess) return hip_check(e, "tree batch upload");
+  launch_phases(ctx, gp, (const BJob *)ctx->tree_table_d,
+                (const BRange *)((uint8_t *)ctx->tree_table_d + jobs_bytes), s);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(ctx->tree_table_done, s);
+  return hip_check(e, "tree batch launch");
+}
+
+void free_tree_batch(v3db_ctx *ctx) {
+  free_tree_batch_tables(ctx);
+  if (ctx->tree_table_staged) (void)hipEventDestroy(ctx->tree_table_staged);
+  if (ctx->tree_table_done) (void)hipEventDestroy(ctx->tree_table_done);
+  ctx->tree_table_staged = ctx->tree_table_done = nullptr;
+}
 
 // The batched LDE passes use the same 8192-word tiles as the single-trace ones.
 v3db_status set_batch_kernel_attributes() {

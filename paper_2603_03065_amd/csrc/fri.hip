@@ -1,9 +1,11 @@
 // FRI commit phase over a codeword on a coset: per round, the Merkle tree whose
-// leaf k hashes the pair (f(x_k), f(-x_k)) = (f[k], f[k + N/2]) (the leaf-hash and
-// Merkle kernels of the trace commitment, reading the codeword as a two-column
+// leaf k hashes the pair (f(x_k), f(-x_k)) = (f[k], f[k + N/2]) (the batched leaf-hash
+// and Merkle kernels of the trace commitment, reading the codeword as a two-column
 // matrix [2][N/2]), then the arity-2 fold with the round's challenge beta:
 //   f'[k] = (f[k] + f[k + N/2]) / 2 + beta (f[k] - f[k + N/2]) / (2 x_k),
 // on the squared coset (shift s^2, N/2 points, natural order).
+#include <vector>
+
 #include "lde_dev.h"
 
 namespace v3db {
@@ -38,53 +40,33 @@ size_t fri_tree_digests(uint32_t log_n, uint32_t rounds, uint32_t cap_height) {
   return d;
 }
 
-// The fold chain runs on the caller's stream; round r's tree only reads f_r, so it
-// runs on side stream r mod FRI_STREAMS once f_r is ready (an event recorded after
-// the fold that produced it) and overlaps the later folds and trees; the caller's
-// stream waits for every side stream before anything enqueued after this call.
+// The fold chain first (each fold reads the previous round's codeword only), then every
+// round's tree in one batch: one leaf-hashing launch over the pair leaves of all rounds
+// and one launch per tree depth over all rounds that still have it, all on the caller's
+// stream.
 v3db_status enqueue_fri_commit(v3db_ctx *ctx, const uint64_t *codeword, uint32_t log_n, uint64_t shift,
                                const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *folded,
                                uint64_t *trees, uint64_t *caps, uint64_t *scratch_tree, hipStream_t stream) {
-  constexpr int NS = v3db_ctx::FRI_STREAMS;
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < NS && e == hipSuccess; i++) {
-    if (!ctx->fri_streams[i]) e = hipStreamCreateWithFlags(&ctx->fri_streams[i], hipStreamNonBlocking);
-    if (e == hipSuccess && !ctx->fri_done[i]) e = hipEventCreateWithFlags(&ctx->fri_done[i], hipEventDisableTiming);
-  }
-  for (uint32_t r = 0; r < rounds && e == hipSuccess; r++)
-    if (!ctx->fri_ready[r]) e = hipEventCreateWithFlags(&ctx->fri_ready[r], hipEventDisableTiming);
-  if (e != hipSuccess) return hip_check(e, "fri streams");
-  const int used = rounds < (uint32_t)NS ? (int)rounds : NS;
+  std::vector<TreeJob> tj(rounds);
   const uint64_t *f = codeword;
   uint64_t *next = folded, *tree = trees ? trees : scratch_tree;
   uint64_t s_r = shift % gl::P;
-  v3db_status st = hip_check(hipEventRecord(ctx->fri_ready[0], stream), "fri fork");
-  for (uint32_t r = 0; r < rounds && st == V3DB_OK; r++) {
+  for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t log_nr = log_n - r;
     const uint64_t half = uint64_t(1) << (log_nr - 1);
-    hipStream_t side = ctx->fri_streams[r % NS];
-    st = hip_check(hipStreamWaitEvent(side, ctx->fri_ready[r], 0), "fri wait");
-    if (st == V3DB_OK) st = enqueue_leaf_hash(ctx, f, 2, log_nr - 1, tree, side);
-    if (st == V3DB_OK)
-      st = enqueue_merkle_levels(ctx, tree, log_nr - 1, cap_height, caps + size_t(r) * (DIGEST << cap_height), side);
-    if (st != V3DB_OK) break;
+    // leaf k = Hash(f_r[k], f_r[k + N_r/2]): the codeword read as the matrix [2][N_r/2]
+    tj[r] = TreeJob{f, tree, caps + size_t(r) * (DIGEST << cap_height), 2, log_nr - 1, cap_height};
     const uint64_t tr = gl::mul(betas[r] % gl::P, gl::inv(s_r));
     const unsigned blocks = (unsigned)std::min<uint64_t>((half + FOLD_THREADS - 1) / FOLD_THREADS, 8192);
     hipLaunchKernelGGL(k_fri_fold, dim3(blocks), dim3(FOLD_THREADS), 0, stream, f, half, log_nr, tr, next, ctx->tw);
-    st = hip_check(hipGetLastError(), "fri fold launch");
-    if (st == V3DB_OK && r + 1 < rounds) st = hip_check(hipEventRecord(ctx->fri_ready[r + 1], stream), "fri ready");
+    v3db_status st = hip_check(hipGetLastError(), "fri fold launch");
+    if (st != V3DB_OK) return st;
     tree += ((uint64_t(2) * half) - (uint64_t(1) << cap_height)) * DIGEST;
     f = next;
     next += half;
     s_r = gl::mul(s_r, s_r);
   }
-  // join every side stream that received work, also after an error
-  for (int i = 0; i < used; i++) {
-    hipError_t j = hipEventRecord(ctx->fri_done[i], ctx->fri_streams[i]);
-    if (j == hipSuccess) j = hipStreamWaitEvent(stream, ctx->fri_done[i], 0);
-    if (st == V3DB_OK && j != hipSuccess) st = hip_check(j, "fri join");
-  }
-  return st;
+  return enqueue_tree_batch(ctx, tj.data(), rounds, stream);
 }
 
 }  // namespace v3db

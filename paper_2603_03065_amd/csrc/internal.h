@@ -105,11 +105,12 @@ struct v3db_ctx {
   hipStream_t capture_stream = nullptr;
   hipStream_t side_stream = nullptr;  // snapshot codebook digest, forked from and joined into the caller's stream
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  // FRI: round trees on side streams, overlapping the fold chain on the caller's stream
-  static constexpr int FRI_STREAMS = 4;
-  hipStream_t fri_streams[FRI_STREAMS] = {};
-  hipEvent_t fri_done[FRI_STREAMS] = {};
-  hipEvent_t fri_ready[V3DB_MAX_LOG_LDE + 1] = {};
+  // batches of Merkle trees over resident matrices (enqueue_tree_batch): the job and
+  // range table on the device, its pinned staging copy, and events marking when the
+  // staging copy has been read and when the last batch's kernels have read the table
+  void *tree_table_d = nullptr, *tree_table_h = nullptr;
+  size_t tree_table_bytes = 0;
+  hipEvent_t tree_table_staged = nullptr, tree_table_done = nullptr;
   std::mutex mu;
 };
 
@@ -166,6 +167,18 @@ void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
 // Batched commits (batch.hip). scratch (nullable) replaces the context's
 // per-stream scratch; it must hold v3db_commit_batch_scratch_bytes(jobs).
 void free_batch_graphs(v3db_ctx *ctx);
+// One Merkle tree of a batch: leaf k hashes row k of mat ([n_cols][2^log_leaves],
+// column-major); the levels go to tree (leaves first, 2^(log_leaves+1) - 2^cap_height
+// digests) and the 2^cap_height cap nodes to cap.
+struct TreeJob {
+  const uint64_t *mat;
+  uint64_t *tree, *cap;
+  uint32_t n_cols, log_leaves, cap_height;
+};
+// Every tree of jobs[0..n) at once: one leaf-hashing launch over all their rows, then one
+// launch per tree depth over all the trees that still have that depth (batch.hip).
+v3db_status enqueue_tree_batch(v3db_ctx *ctx, const TreeJob *jobs, size_t n, hipStream_t stream);
+void free_tree_batch(v3db_ctx *ctx);
 size_t fri_tree_digests(uint32_t log_n, uint32_t rounds, uint32_t cap_height);
 v3db_status enqueue_fri_commit(v3db_ctx *ctx, const uint64_t *codeword, uint32_t log_n, uint64_t shift,
                                const uint64_t *betas, uint32_t rounds, uint32_t cap_height, uint64_t *folded,
