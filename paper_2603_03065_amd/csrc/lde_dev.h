@@ -433,6 +433,56 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
 // Pass 3, tile = T consecutive columns e of Z (of column col). In natural
 // layout the words it reads, Z[k1][e] at k1*W + e, are exactly the words it
 // writes, LDE[e + W*m2], so it can run in place.
+// The first radix-8 pass of a row transform (sub-blocks of the whole row, 2^logM words)
+// with its inputs read straight from global memory: word w of row t is src(t, w). The
+// butterflies are numbered with t fastest, so with T >= 16 rows the lanes of a
+// half-wave read 16 consecutive words (the rows are adjacent columns of a matrix).
+template <bool INV, class Src>
+__device__ __forceinline__ void first_pass_global(uint64_t *sh, int T, int logT, int logM, int rs,
+                                                  const uint64_t *__restrict__ bfly, Src src) {
+  const int logStride = logM - 3, stride = 1 << logStride;
+  const int nb = T << logStride;
+  const uint64_t *rows = bfly + 8 * bfly_row0(logM);
+  for (int b = threadIdx.x; b < nb; b += LDE_THREADS) {
+    const int t = b & (T - 1), i = b >> logT;
+    uint64_t v[8], w[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = src(t, i + (j << logStride));
+    const ulonglong2 *trow = reinterpret_cast<const ulonglong2 *>(rows + 8 * i);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const ulonglong2 x = trow[k];
+      w[2 * k] = x.x, w[2 * k + 1] = x.y;
+    }
+    reg_dif<8, INV>(v);
+    uint64_t *row = sh + t * rs;
+    const int wb = swz(i);
+    row[wb] = v[0];
+#pragma unroll
+    for (int j = 1; j < 8; j++) row[wb ^ swz(j << logStride)] = gl::mul(v[j], w[j]);
+  }
+}
+
+// The last pass of a row transform (radix R on sub-blocks of R consecutive words, no
+// twiddles) with its outputs written straight to global memory: position w of row t
+// (frequency bitrev(w)) goes to dst(t, w, value). Butterflies numbered with t fastest.
+template <int R, bool INV, class Dst>
+__device__ __forceinline__ void last_pass_global(const uint64_t *sh, int T, int logT, int logM, int rs, Dst dst) {
+  constexpr int LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int nb = T << (logM - LR);
+  for (int b = threadIdx.x; b < nb; b += LDE_THREADS) {
+    const int t = b & (T - 1), q = b >> logT;
+    const uint64_t *row = sh + t * rs;
+    const int wb = swz(q << LR);
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = row[wb ^ swz(j)];
+    reg_dif<R, INV>(v);
+#pragma unroll
+    for (int j = 0; j < R; j++) dst(t, (q << LR) + j, v[j]);
+  }
+}
+
 __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
                                                int tile) {
   const int n1 = 1 << s.L1, T = 1 << s.logT3, rs = n1 + 1;
@@ -442,6 +492,25 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
   uint64_t *out = s.lde + size_t(col) * N;
   const int e0 = tile << s.logT3;
   const int total = T * n1;
+  if (!s.bitrev && s.L1 >= 4) {
+    // natural layout, at least two passes: the first reads Z straight from global
+    // memory and the last writes the output straight to it, saving a round trip
+    // through LDS and a barrier at each end. Z is the output column itself (the tile's
+    // words are read before the first barrier and written after the last one).
+    first_pass_global<false>(sh, T, s.logT3, s.L1, rs, tw.bfly_fwd,
+                             [&](int t, int w) { return zc[(size_t(w) << LW) + e0 + t]; });
+    __syncthreads();
+    const int last = s.L1 % 3 == 0 ? 3 : s.L1 % 3;  // log2 of the last pass's radix
+    for (int logS = s.L1 - 3; logS > last; logS -= 3) {
+      dif_pass<8, false, true>(sh, T, s.L1, rs, logS, tw.bfly_fwd);
+      __syncthreads();
+    }
+    auto dst = [&](int t, int w, uint64_t v) { out[size_t(e0 + t) + size_t(W) * brev(w, s.L1)] = v; };
+    if (last == 3) last_pass_global<8, false>(sh, T, s.logT3, s.L1, rs, dst);
+    else if (last == 2) last_pass_global<4, false>(sh, T, s.logT3, s.L1, rs, dst);
+    else last_pass_global<2, false>(sh, T, s.logT3, s.L1, rs, dst);
+    return;
+  }
   stage_tile(
       total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
       [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT3)] = v; });
