@@ -78,3 +78,30 @@ def test_fri_rejects_bad_arguments(v3db):
             ctx.fri_commit(f, 7, [1, 2, 3], 2)
         with pytest.raises(v3db.V3dbError, match="shift"):
             ctx.fri_commit(f, P, [1], 0)
+
+
+def test_fri_calls_of_different_sizes_on_one_context(v3db, poseidon, oracle_mod):
+    """Back-to-back calls on one context whose round tables differ in size (the batched
+    trees' job table grows, then is reused for a smaller call), the middle one on
+    another stream: every call equals the oracle."""
+    import torch
+    oracle_mod.set_threads(0)
+    shapes = [(9, 3, 2), (14, 10, 3), (7, 2, 1)]   # (log_n, rounds, cap height)
+    side = torch.cuda.Stream()
+    with v3db.Context(0) as ctx:
+        outs = []
+        for k, (log_n, rounds, h) in enumerate(shapes):
+            f0 = inputs.canon(inputs.splitmix64(130 + k, np.arange(1 << log_n, dtype=np.uint64)))
+            betas = [int(b) % P for b in inputs.splitmix64(140 + k, np.arange(rounds, dtype=np.uint64))]
+            stream = side if k == 1 else None
+            d = v3db.to_device(f0)
+            if stream is not None:
+                stream.wait_stream(torch.cuda.current_stream())
+            folded, caps, trees = ctx.fri_commit(d, 7, betas, h, want_trees=True, stream=stream)
+            outs.append((f0, betas, h, folded, caps, trees))
+        torch.cuda.synchronize()
+        for f0, betas, h, folded, caps, trees in outs:
+            ofolded, ocaps, otrees = poseidon.fri_commit(f0, 7, betas, h, want_trees=True)
+            assert np.array_equal(v3db.to_host(folded), ofolded)
+            assert np.array_equal(v3db.to_host(caps), ocaps)
+            assert np.array_equal(v3db.to_host(trees), otrees)
