@@ -100,9 +100,12 @@ def measured_traffic(kernel: str, workload: str):
     except (OSError, KeyError, ValueError):
         return None
     h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
+    try:
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, TypeError):
+        return None
     if h.hexdigest()[:16] != rec["source_digest"] or rec["workload"] != workload:
         return None
     return rec["hbm_bytes_per_dispatch"]
