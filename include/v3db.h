@@ -153,7 +153,7 @@ typedef struct {
 } v3db_commit_job;
 
 /* Commit many independent traces of different shapes. Natural-layout jobs are
- * committed together, phase by phase: every phase (the three extension passes,
+ * committed together, phase by phase: every phase (each extension pass,
  * leaf hashing, each tree depth) runs as one launch over the work of all jobs,
  * so small traces share the GPU. The launch sequence for a given list of shapes
  * (per stream) is captured once as a HIP graph and replayed; only a small table
@@ -296,11 +296,13 @@ v3db_status v3db_fri_commit(v3db_ctx *ctx, const uint64_t *d_codeword, uint32_t 
 
 /* ---------------------------------------------------------------- schedules
  * How the extension of one shape (log_rows, log_blowup) is cut into kernels. The
- * size-n transforms are four-step (n = n1 * n2, Sec. 5.2 "NTT and LDE kernels"):
- * pass 1 runs inverse size-n1 sub-transforms in tiles of 2^t1 columns, pass 2 the
- * inverse size-n2 and forward size-(B n2) transforms in tiles of 2^t2 rows, pass 3
- * the forward size-n1 transforms in tiles of 2^t3 columns; the single-trace path
- * runs passes 2 and 3 over chunk_cols columns at a time. A schedule never changes
+ * size-n transforms (the FFT-based polynomial operations of Sec. 2.1 para. "Gate
+ * counts and proving time") are computed four-step, n = n1 * n2, a choice of this
+ * library: pass 1 runs inverse size-n1 sub-transforms in tiles of 2^t1 columns,
+ * pass 2i the inverse size-n2 transforms in tiles of up to 16 rows, pass 2 the
+ * forward size-(B n2) transforms in tiles of 2^t2 rows, pass 3 the forward size-n1
+ * transforms in tiles of 2^t3 columns; the single-trace path runs passes 2 and 3
+ * over chunk_cols columns at a time. A schedule never changes
  * results, only speed. Every context starts with a default schedule for each shape;
  * v3db_autotune_lde times candidates on the device and installs the fastest.
  *   split_log   log2 n2: n1 = 2^(log_rows - split_log) <= 4096, n2 <= 4096,

@@ -55,7 +55,7 @@ struct LdeSchedule {
 // Per-shape LDE tables: see ntt.hip.
 struct LdePlan {
   uint32_t log_rows, log_blowup, L1, L2;
-  uint32_t logT1, logT2, logT3;  // log2 tile heights of the three passes
+  uint32_t logT1, logT2, logT3;  // log2 tile heights of passes 1, 2 and 3
   uint32_t logT2i;               // log2 rows per tile of pass 2's inverse part (run as its own kernel)
   uint32_t chunk;                // columns per pass-2/3 round (single-trace path)
   uint64_t shift;

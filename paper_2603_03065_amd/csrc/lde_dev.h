@@ -3,7 +3,7 @@
 //
 // For a column a of n = 2^L values (a_i = P(w_n^i)), the extension to N = B*n
 // points is LDE[k] = P(s * w_N^k) = sum_j c_j (s w_N^k)^j with c = iNTT_n(a).
-// It runs as three LDS-tiled passes of a four-step factorisation, n = n1*n2:
+// It runs as LDS-tiled passes of a four-step factorisation, n = n1*n2:
 //
 //   pass 1  (interpolation, first half)   j = j1*n2 + j2, k = k1 + n1*k2
 //           Y[k1][j2] = w_n^(-j2 k1) * sum_j1 a[j1 n2 + j2] w_n1^(-j1 k1)

@@ -1,5 +1,5 @@
-// Coset low-degree extension of one trace: tables, plans and the three pass
-// kernels (the pass bodies and the transform engine are in lde_dev.h).
+// Coset low-degree extension of one trace: tables, plans and the pass kernels
+// (1, 2i, 2, 3; the pass bodies and the transform engine are in lde_dev.h).
 #include "lde_dev.h"
 
 namespace v3db {
