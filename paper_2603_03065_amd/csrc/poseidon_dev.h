@@ -164,9 +164,12 @@ constexpr int WIDE_GROUP = 16;
 constexpr int WIDE_THREADS = 64;  // one wave: 4 permutations
 constexpr int WIDE_PER_BLOCK = WIDE_THREADS / WIDE_GROUP;
 
+// lane J of each 16-lane row, at every lane of the row (v_mov_b64_dpp row_newbcast:J).
+// Every lane has a source, so no previous value of the destination is kept and the
+// compiler needs no zeroing move before it.
 template <int J>
 __device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
-  return (uint64_t)__builtin_amdgcn_update_dpp((long)0, (long)v, 0x150 + J, 0xf, 0xf, false);  // v_mov_b64_dpp
+  return (uint64_t)__builtin_amdgcn_mov_dpp((long)v, 0x150 + J, 0xf, 0xf, true);
 }
 
 template <int J>
@@ -267,9 +270,10 @@ __device__ __forceinline__ void rows_both(uint64_t v, uint64_t &even, uint64_t &
   odd = ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1];
 }
 
-// lane i of each row receives lane i + 6 of the row (DPP row_shl:6; lanes 10..15 get 0)
+// lane i of each row receives lane i + 6 of the row (DPP row_shl:6; lanes 10..15 have
+// no source and read 0 under bound_ctrl)
 __device__ __forceinline__ uint64_t row_shl6(uint64_t v) {
-  return (uint64_t)__builtin_amdgcn_update_dpp((long)0, (long)v, 0x106, 0xf, 0xf, false);
+  return (uint64_t)__builtin_amdgcn_mov_dpp((long)v, 0x106, 0xf, 0xf, true);
 }
 
 template <int J>
