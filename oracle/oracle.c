@@ -282,9 +282,12 @@ void or_poseidon_permute(const or_poseidon_params *pp, uint64_t s[OR_WIDTH]) {
     for (int i = 0; i < (full ? OR_WIDTH : 1); i++) s[i] = or_pow(s[i], 7);
     uint64_t t[OR_WIDTH];
     for (int i = 0; i < OR_WIDTH; i++) {
-      uint64_t acc = 0;
-      for (int j = 0; j < OR_WIDTH; j++) acc = or_add(acc, or_mul(pp->mds[i][j], s[j]));
-      t[i] = acc;
+      /* (M s)_i = sum_j M[i][j] s_j mod p. The entries are 1 + (z mod 255) <= 255, so
+       * the twelve products sum to less than 12 * 2^8 * 2^64 < 2^76: the sum is exact in
+       * 128 bits and is reduced once. */
+      u128 acc = 0;
+      for (int j = 0; j < OR_WIDTH; j++) acc += (u128)pp->mds[i][j] * s[j];
+      t[i] = (uint64_t)(acc % OR_P);
     }
     memcpy(s, t, sizeof(t));
   }

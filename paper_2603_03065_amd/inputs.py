@@ -105,3 +105,43 @@ def snapshot(seed: int, log_lists: int, log_slots: int, m: int, dim: int, k: int
     centroids = _fixed_point(seed, 4, n_list * dim).reshape(n_list, dim)
     codebooks = _fixed_point(seed, 5, k * dim).reshape(m, k, dim // m)
     return {"flag": flag, "item": item, "codes": codes, "centroids": centroids, "codebooks": codebooks}
+
+
+# ---- serving workload -----------------------------------------------------------
+
+SERVE_ARRIVAL_STREAM = 0x5634_0005   # exponential inter-arrival gaps
+SERVE_BIG_STREAM = 0x5634_0105       # u' < 0.05: an 80 x 2^18 request (cap height 4)
+SERVE_SHAPE_STREAM = 0x5634_0205     # otherwise the batch workload's shape distribution
+SERVE_SAMPLE_STREAM = 0x5634_0305    # the seeded 2 % sample of requests checked against stored caps
+SERVE_TRACE_SEED = 5                 # request i's trace is trace(5, i, n_cols, log_rows)
+SERVE_BIG_SHAPE = (18, 80, 4)        # (log_rows, n_cols, cap_height)
+
+
+def serve_requests(seconds: float = 120.0, rate: float = 50.0):
+    """Seeded open-loop arrivals: list of (t_arrive_s, log_rows, n_cols, cap_height)
+    for request index i = 0, 1, ... Gaps are -ln(1 - u) / rate with u from
+    SERVE_ARRIVAL_STREAM; a request is 80 cols x 2^18 rows with cap height 4 when
+    u' < 0.05 (SERVE_BIG_STREAM), otherwise log rows 10 + (z mod 9) and columns
+    20 + (z' mod 116) with cap height 2 (SERVE_SHAPE_STREAM, outputs 2i and 2i + 1)."""
+    import math
+    out, t, i = [], 0.0, 0
+    while True:
+        u = float(uniform01(SERVE_ARRIVAL_STREAM, i))
+        t += -math.log(1.0 - u) / rate
+        if t >= seconds:
+            return out
+        if float(uniform01(SERVE_BIG_STREAM, i)) < 0.05:
+            L, C, h = SERVE_BIG_SHAPE
+        else:
+            L = 10 + int(splitmix64(SERVE_SHAPE_STREAM, 2 * i)) % 9
+            C = 20 + int(splitmix64(SERVE_SHAPE_STREAM, 2 * i + 1)) % 116
+            h = 2
+        out.append((t, L, C, h))
+        i += 1
+
+
+def serve_checked(requests):
+    """Indices of the requests whose caps are stored as expected values: a seeded 2 %
+    sample (u < 0.02 on SERVE_SAMPLE_STREAM) and every 80 x 2^18 request."""
+    return [i for i, (_, L, C, h) in enumerate(requests)
+            if float(uniform01(SERVE_SAMPLE_STREAM, i)) < 0.02 or (L, C, h) == SERVE_BIG_SHAPE]

@@ -83,3 +83,73 @@ class InversePoseidon:
                 s[i] = pow(s[i], D_INV7, P)
             s = [(s[i] - self.rc[r][i]) % P for i in range(12)]
         return s
+
+
+# ---------------------------------------------------------------- forward permutation
+
+MASK64 = (1 << 64) - 1
+SM_GAMMA = 0x9E3779B97F4A7C15
+SM_M1, SM_M2 = 0xBF58476D1CE4E5B9, 0x94D049BB133111EB
+
+
+def splitmix64(seed, i):
+    """Output i (0-based) of SplitMix64 started at seed (Steele, Lea, Flood 2014): the
+    state advances by the golden-ratio increment before each output, then the
+    published finaliser (xor-shift 30, multiply, xor-shift 27, multiply, xor-shift 31)."""
+    z = (seed + (i + 1) * SM_GAMMA) & MASK64
+    z = ((z ^ (z >> 30)) * SM_M1) & MASK64
+    z = ((z ^ (z >> 27)) * SM_M2) & MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix64_seed_for(target, index):
+    """A seed whose stream has output `target` at `index`: the finaliser is a bijection
+    (xor-shifts and multiplications by odd constants undo), so the state that yields
+    target is found by running it backwards, and the seed is that state minus
+    (index + 1) increments."""
+    def unxorshift(y, s):
+        x = y
+        for _ in range(64 // s + 1):
+            x = y ^ (x >> s)
+        return x
+    x = unxorshift(target, 31)
+    x = (x * pow(SM_M2, -1, 1 << 64)) & MASK64
+    x = unxorshift(x, 27)
+    x = (x * pow(SM_M1, -1, 1 << 64)) & MASK64
+    x = unxorshift(x, 30)
+    return (x - (index + 1) * SM_GAMMA) & MASK64
+
+
+class ForwardPoseidon:
+    """The width-12 permutation written directly from its definition with Python
+    integers: for each of the 30 rounds, add the round's constants to every lane, raise
+    every lane (rounds 0-3 and 26-29) or lane 0 only (the 22 partial rounds) to the 7th
+    power, then replace the state by M times it, M[i][j] = circ[(j - i) mod 12]."""
+
+    def __init__(self, rc, circ, full_half=4, rounds=30):
+        self.rc = [[int(v) for v in row] for row in rc]
+        self.circ = [int(v) for v in circ]
+        self.full_half, self.rounds = full_half, rounds
+
+    def __call__(self, state):
+        s = [int(v) % P for v in state]
+        for r in range(self.rounds):
+            full = r < self.full_half or r >= self.rounds - self.full_half
+            s = [(s[i] + self.rc[r][i]) % P for i in range(12)]
+            for i in range(12 if full else 1):
+                s[i] = pow(s[i], 7, P)
+            s = [sum(self.circ[(j - i) % 12] * s[j] for j in range(12)) % P for i in range(12)]
+        return s
+
+    def sponge(self, row):
+        """Zero state; each chunk of up to 8 elements overwrites lanes 0..k-1, then one
+        permutation. Returns the whole final state (digest = lanes 0..3)."""
+        s = [0] * 12
+        for q in range(0, len(row), 8):
+            chunk = [int(v) for v in row[q:q + 8]]
+            s[:len(chunk)] = chunk
+            s = self(s)
+        return s
+
+    def compress(self, left, right):
+        return self([int(v) for v in left] + [int(v) for v in right] + [0, 0, 0, 0])[:4]
