@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Commit throughput on one MI355X: coset LDE + Poseidon leaf hashing + Merkle cap.
 
-A step is one whole commit (v3db_commit_batch with one job: three LDE passes,
-the leaf sponge over every extended row, every Merkle level up to the cap) of a
-synthetic trace already resident in HBM. Default workload: 80 columns x 2^18
-rows of uniform Goldilocks elements, blowup 8 (2^21 extended rows), rate-8
-sponge rows, cap height 4, natural layout.
+A step is one whole commit (v3db_commit_batch with one job: the LDE passes, the
+leaf sponge over every extended row, every Merkle level up to the cap) of a
+synthetic trace already resident in HBM. Default workload: the largest single
+trace, 135 columns x 2^20 rows of uniform Goldilocks elements, blowup 8 (2^23
+extended rows, 9.06 GB), rate-8 sponge rows, cap height 4, bit-reversed layout.
 
 Prints one JSON line: LDE elements committed per second (value), per-step
-p50/p99 latency, the dominant kernel against its roofline (timed live with HIP
-events on the library's stream), and the CPU oracle timed on a bounded sample.
+p50/p99 latency with a 95 % interval for the median, the trace upload from pinned
+host memory timed apart, the dominant kernel against its roofline (timed live with
+HIP events on the library's stream), the 64-trace batch committed by one batched
+call against one launch sequence per trace, and the CPU oracle timed on bounded
+samples at one thread and at every host thread.
 """
 from __future__ import annotations
 
@@ -44,7 +47,7 @@ SNAPSHOT_WORKLOADS = {
     "snapshot-sift1m": ("SIFT1M zk-opt layout: 1024 lists x 2048 slots (N = 2^21), M = 8, D = 128, K = 256", 10, 11, 8, 128, 256, 6),
     "snapshot-gist1m": ("GIST1M zk-opt layout: 512 lists x 4096 slots (N = 2^21), M = 8, D = 960, K = 256", 9, 12, 8, 960, 256, 7),
 }
-DEFAULT_WORKLOAD = "commit-80x2^18"
+DEFAULT_WORKLOAD = "commit-135x2^20"
 
 # Peaks of one MI355X (gfx950): 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU
 # issue (v_mad_u64_u32 and v_mul_hi_u32 are full rate on this chip), 8 TB/s HBM3E.
@@ -129,27 +132,70 @@ def parse():
                     help="keep the default LDE schedules instead of tuning them before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (reference for the HBM byte counters)")
-    ap.add_argument("--cpu-sample-log-rows", type=int, default=17,
-                    help="rows (log2) of the oracle's sample trace; same columns/blowup/cap as the workload")
+    ap.add_argument("--cpu-sample-log-rows", type=int, default=15,
+                    help="rows (log2) of the oracle's all-thread sample; same columns/layout/blowup/cap as the workload")
+    ap.add_argument("--cpu-sample-log-rows-1t", type=int, default=12,
+                    help="rows (log2) of the oracle's one-thread sample")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="single-trace workloads: leave out the 64-trace batched vs per-trace comparison")
     return ap.parse_args()
 
 
-def cpu_baseline(n_cols, log_blowup, cap_height, layout, log_rows):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n_cols, log_blowup, cap_height, layout, log_rows, log_rows_1t):
+    """The CPU oracle (plain C, OpenMP over columns, rows and nodes) committing a trace
+    with the workload's columns, layout, blowup and cap height but fewer rows: once on
+    every host thread and once on one thread."""
     import oracle
     from paper_2603_03065_amd import inputs
-    tr = inputs.trace(99, 0, n_cols, log_rows)
-    threads = oracle.set_threads(0)
     pos = oracle.Poseidon(260303065)
-    t0 = time.perf_counter()
-    pos.commit(tr, log_blowup, 7, layout, min(cap_height, log_rows + log_blowup))
-    dt = time.perf_counter() - t0
-    elems = n_cols << (log_rows + log_blowup)
+
+    def one(threads, lr):
+        tr = inputs.trace(99, 0, n_cols, lr)
+        used = oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        pos.commit(tr, log_blowup, 7, layout, min(cap_height, lr + log_blowup))
+        dt = time.perf_counter() - t0
+        return used, dt, n_cols << (lr + log_blowup)
+
+    lay = "bit-reversed" if layout else "natural"
+    t_all, dt_all, e_all = one(0, log_rows)
+    t_one, dt_one, e_one = one(1, log_rows_1t)
+    oracle.set_threads(0)
     return {
-        "value": elems / dt, "unit": "LDE field elems/s", "cores": threads, "kind": "oracle",
-        "seconds": dt,
-        "sample": f"one whole commit of {n_cols} cols x 2^{log_rows} rows (blowup {1 << log_blowup}, "
-                  f"cap height {cap_height}, same column count as the workload, fewer rows) on {threads} host threads",
+        "value": e_all / dt_all, "unit": "LDE field elems/s", "cores": t_all, "kind": "oracle",
+        "seconds": dt_all, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+        "sample": f"one whole commit of {n_cols} cols x 2^{log_rows} rows ({lay}, blowup {1 << log_blowup}, "
+                  f"cap height {cap_height}: the workload's columns and layout, fewer rows) on {t_all} host threads",
+        "one_thread": {"value": e_one / dt_one, "unit": "LDE field elems/s", "cores": t_one, "seconds": dt_one,
+                       "sample": f"one whole commit of {n_cols} cols x 2^{log_rows_1t} rows ({lay}, blowup "
+                                 f"{1 << log_blowup}, cap height {cap_height}) on 1 thread"},
     }
+
+
+def median_ci95(x):
+    """Distribution-free 95 % interval for the median of the samples x: the order
+    statistics j, k of the binomial(n, 1/2) bounds (None for fewer than 6 samples)."""
+    import numpy as np
+    xs = np.sort(np.asarray(x, dtype=np.float64))
+    n = len(xs)
+    if n < 6:
+        return None
+    cdf = np.cumsum([math.comb(n, i) for i in range(n + 1)]) / 2.0 ** n
+    i = int(np.searchsorted(cdf, 0.025))   # smallest i with P(B <= i) >= 0.025
+    # lower bound: order statistic i (1-based) since P(B <= i - 1) < 0.025; upper: n + 1 - i
+    return [float(xs[i - 1]), float(xs[n - i])]
 
 
 def schedule_json(s):
@@ -158,6 +204,15 @@ def schedule_json(s):
 
 
 def batch_main(args):
+    """The batched workload on its own line."""
+    out = batch_measure(args, args.steps, args.warmup)
+    out.update({"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                "data": "synthetic"})
+    print(json.dumps(out), flush=True)
+
+
+def batch_measure(args, steps, warmup):
     """64 traces of mixed shapes committed by one v3db_commit_batch call (batched
     phase launches replayed from a HIP graph), against the same jobs committed
     one trace at a time (one launch sequence per trace)."""
@@ -201,28 +256,65 @@ def batch_main(args):
         wall = time.perf_counter() - t0
         return wall, np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(steps)])
 
-    wall_b, ms_b = run(True, args.steps, args.warmup)
-    wall_s, ms_s = run(False, max(2, args.steps // 2), 1)
+    wall_b, ms_b = run(True, steps, warmup)
+    wall_s, ms_s = run(False, max(2, steps // 2), 1)
+    ctx.set_batching(True)
+    caps = [v3db.to_host(j.cap) for j in jobs]
     out = {
-        "metric": METRIC,
-        "value": elems * args.steps / wall_b,
+        "value": elems * steps / wall_b,
         "unit": "LDE field elems/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall_b * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
+        "ms_per_step": wall_b * 1e3 / steps,
         "config": {"workload": f"{BATCH_WORKLOAD}: 64 traces, log rows uniform in 10..18, columns uniform in "
                                "20..135, blowup 8, cap height 2, natural layout, one v3db_commit_batch call",
                    "lde_elements_per_step": elems,
                    "shapes": [[L, C] for L, C in shapes]},
         "lde_schedules": tuned or "default",
-        "latency_ms": {"p50": float(np.percentile(ms_b, 50)), "p99": float(np.percentile(ms_b, 99))},
+        "latency_ms": {"p50": float(np.percentile(ms_b, 50)), "p99": float(np.percentile(ms_b, 99)),
+                       "p50_ci95": median_ci95(ms_b)},
         "one_launch_per_trace": {"value": elems * len(ms_s) / wall_s, "ms_per_step": wall_s * 1e3 / len(ms_s),
-                                 "p50_ms": float(np.percentile(ms_s, 50))},
-        "batched_over_per_trace": (elems * args.steps / wall_b) / (elems * len(ms_s) / wall_s),
+                                 "steps": len(ms_s), "p50_ms": float(np.percentile(ms_s, 50)),
+                                 "p99_ms": float(np.percentile(ms_s, 99))},
+        "batched_over_per_trace": (elems * steps / wall_b) / (elems * len(ms_s) / wall_s),
+        "caps_sha256": caps_digest(caps),
+        "cap_check": golden_check(BATCH_WORKLOAD, caps),
     }
     ctx.close()
-    print(json.dumps(out), flush=True)
+    del jobs
+    torch.cuda.empty_cache()
+    return out
+
+
+GOLDEN_CAPS = {"commit-8x2^12": "caps_small.json", "commit-80x2^18": "caps_80x2p18.json",
+               "commit-135x2^20": "caps_135x2p20.json", BATCH_WORKLOAD: "caps_batch64.json"}
+
+
+def golden_check(workload: str, caps):
+    """Compare the caps the GPU produced (one per trace, in entry order) with the expected
+    caps the CPU oracle wrote under tests/golden/ (tests/golden/make_caps.py)."""
+    import numpy as np
+    name = GOLDEN_CAPS.get(workload)
+    path = os.path.join(ROOT, "tests", "golden", name) if name else None
+    if not path or not os.path.exists(path):
+        return {"golden": None, "note": "no stored oracle caps for this workload"}
+    with open(path) as f:
+        entries = json.load(f)["entries"]
+    if len(entries) != len(caps):
+        return {"golden": name, "note": f"{len(entries)} stored entries for {len(caps)} caps", "matched": 0,
+                "of": len(caps)}
+    ok = sum(int(np.array_equal(np.asarray(c, dtype=np.uint64).reshape(-1, 4),
+                                np.array([[int(w, 16) for w in row] for row in e["cap"]], dtype=np.uint64)))
+             for c, e in zip(caps, entries))
+    return {"golden": name, "matched": ok, "of": len(caps), "bit_exact": ok == len(caps)}
+
+
+def caps_digest(caps) -> str:
+    """SHA-256 over the caps (canonical u64 words, little-endian, in job order)."""
+    import hashlib
+    import numpy as np
+    h = hashlib.sha256()
+    for c in caps:
+        h.update(np.ascontiguousarray(c, dtype=np.uint64).tobytes())
+    return h.hexdigest()
 
 
 def open_main(args):
@@ -468,91 +560,151 @@ def multiset_main(args):
 SERVE_WORKLOAD = "serve-poisson"
 
 
-def serve_requests(seconds, rate):
-    """Seeded open-loop arrivals: exponential gaps (rate per second) from
-    SplitMix64 stream 0x56340005; a request is 80 cols x 2^18 rows (cap height 4)
-    with probability 0.05 (stream 0x56340105), else drawn from the batch
-    workload's distribution (stream 0x56340205: log rows 10..18, cols 20..135,
-    cap height 2)."""
-    import math as m
-    from paper_2603_03065_amd import inputs
-    out, t, i = [], 0.0, 0
-    while True:
-        u = float(inputs.uniform01(0x56340005, i))
-        t += -m.log(1.0 - u) / rate
-        if t >= seconds:
-            return out
-        big = float(inputs.uniform01(0x56340105, i)) < 0.05
-        if big:
-            L, C, h = 18, 80, 4
-        else:
-            L = 10 + int(inputs.splitmix64(0x56340205, 2 * i)) % 9
-            C = 20 + int(inputs.splitmix64(0x56340205, 2 * i + 1)) % 116
-            h = 2
-        out.append((t, L, C, h))
-        i += 1
+class TraceFeeder:
+    """Draws each request's trace (seed 5, trace = request index) on the device, copies it
+    into pinned host memory and hands it over in arrival order, running ahead of the
+    arrival clock on its own thread so no submission waits for its trace. Pinned buffers
+    come from power-of-two size classes and go back to the pool once their request is done."""
+
+    def __init__(self, reqs, lookahead=24):
+        import queue
+        import threading
+
+        import torch
+        self.reqs = reqs
+        self.pool = {}
+        self.lock = threading.Lock()
+        self.ready = queue.Queue(maxsize=lookahead)
+        self.pinned_bytes = 0
+        self.stream = torch.cuda.Stream()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _buffer(self, words):
+        import torch
+        k = max(16, (words - 1).bit_length())
+        with self.lock:
+            free = self.pool.setdefault(k, [])
+            if free:
+                return free.pop()
+        self.pinned_bytes += 8 << k
+        return torch.empty((1 << k,), dtype=torch.int64, pin_memory=True)
+
+    def release(self, buf):
+        with self.lock:
+            self.pool[buf.numel().bit_length() - 1].append(buf)
+
+    def _run(self):
+        import torch
+
+        from paper_2603_03065_amd import inputs
+        with torch.cuda.stream(self.stream):
+            for i, (_, L, C, _) in enumerate(self.reqs):
+                buf = self._buffer(C << L)
+                dev = inputs.trace_torch(inputs.SERVE_TRACE_SEED, i, C, L, device="cuda")
+                buf[:C << L].copy_(dev.view(-1))
+                del dev
+                self.ready.put(buf)
+
+    def next(self):
+        return self.ready.get()
 
 
 def serve_main(args):
-    """Open-loop Poisson arrivals into the continuous-batching server, then the
-    same arrivals into a one-request-at-a-time FIFO server; plus saturation
-    throughput of both with every request queued at once."""
+    """Open-loop Poisson arrivals into the continuous-batching server, then the same
+    arrivals into a one-request-at-a-time FIFO server; plus saturation throughput of
+    both with every request queued at once. Every request commits its own seeded trace;
+    the caps of the requests stored by the oracle (tests/golden/caps_serve.json) are
+    compared with what the server returned."""
     import numpy as np
     import torch
 
     import paper_2603_03065_amd as v3db
     from paper_2603_03065_amd import inputs
 
-    reqs = serve_requests(args.serve_seconds, args.serve_rate)
-    host = torch.from_numpy(inputs.trace(5, 0, 135, 18).reshape(-1).view(np.int64)).pin_memory()
+    reqs = inputs.serve_requests(args.serve_seconds, args.serve_rate)
+    golden = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "caps_serve.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            golden = {int(i): e for i, e in json.load(f)["entries"].items()}
     ctx = v3db.Context(0)
 
-    def run(slots, max_batch, arrivals, open_loop):
+    def run(slots, max_batch, arrivals, open_loop, label):
         srv = v3db.Server(ctx, slots=slots, hbm_budget=64 << 30, max_batch=max_batch)
-        # warm the pool and the kernels
-        for L, C, h in {(18, 80, 4), (14, 60, 2)}:
-            srv.submit(host, cap_height=h, shape=(C, L))
+        # warm the kernels of both request kinds (their own traces, not timed)
+        warm = [inputs.trace(9, k, C, L) for k, (L, C) in enumerate([(18, 80), (14, 60)])]
+        for w, h in zip(warm, (4, 2)):
+            srv.submit(w, cap_height=h)
         srv.drain()
-        t0 = v3db.clock() + 0.05
-        tickets = []
+        # closed loop: every trace is drawn before the clock starts, so the feeder cannot
+        # be what limits the measured throughput
+        feeder = TraceFeeder(arrivals, lookahead=24 if open_loop else len(arrivals))
+        if not open_loop:
+            feeder.thread.join()
+        out = {}                        # request index -> (t_arrive, LDE elements, timing, cap)
+        pending = []
+        t0 = v3db.clock() + 0.5         # the feeder's lead
         next_note = 10.0
-        for (t, L, C, h) in arrivals:
-            if open_loop and t >= next_note:
-                print(f"serve: slots={slots} max_batch={max_batch} t={t:.0f}s submitted={len(tickets)}",
-                      file=sys.stderr, flush=True)
-                next_note += 10.0
+
+        def reap():
+            keep = []
+            for i, tk, buf in pending:
+                r = srv.poll(tk)
+                if r is None:
+                    keep.append((i, tk, buf))
+                    continue
+                feeder.release(buf)
+                st, cap, tm = r
+                assert st == 0, f"request {i} failed"
+                t, L, C, _ = arrivals[i]
+                out[i] = (t, C << (L + 3), tm, cap)
+            pending[:] = keep
+
+        for i, (t, L, C, h) in enumerate(arrivals):
+            buf = feeder.next()
             target = t0 + (t if open_loop else 0.0)
             while open_loop and v3db.clock() < target:
-                time.sleep(min(0.002, max(0.0, target - v3db.clock())))
-            tickets.append((srv.submit(host, cap_height=h, shape=(C, L), t_arrive=target), t, L, C))
+                reap()
+                time.sleep(min(0.001, max(0.0, target - v3db.clock())))
+            if open_loop and t >= next_note:
+                print(f"serve {label}: t={t:.0f}s submitted={i}", file=sys.stderr, flush=True)
+                next_note += 10.0
+            tk = srv.submit(buf[:C << L], cap_height=h, shape=(C, L), t_arrive=target if open_loop else -1.0)
+            pending.append((i, tk, buf))
         srv.drain()
-        rows = []
-        for tk, t, L, C in tickets:
-            st, cap, tm = srv.poll(tk)
-            assert st == 0
-            rows.append((t, C << (L + 3), tm["t_done"] - tm["t_arrive"], tm["t_done"] - t0, tm["batch_size"]))
+        reap()
         stats = srv.stats()
         srv.close()
-        return rows, stats
+        t_origin = t0 if open_loop else min(o[2]["t_arrive"] for o in out.values())
+        rows = [(out[i][0], out[i][1], out[i][2]["t_done"] - out[i][2]["t_arrive"], out[i][2]["t_done"] - t_origin,
+                 out[i][2]["batch_size"]) for i in range(len(arrivals))]
+        caps = {i: out[i][3] for i in out}
+        print(f"serve {label}: done, pinned {feeder.pinned_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+        return rows, stats, caps
 
-    def summarize(rows, warm):
-        sel = [r for r in rows if r[0] >= warm]
+    def summarize(rows, lo, hi=None):
+        sel = [r for r in rows if r[0] >= lo and (hi is None or r[0] < hi)]
         lat = np.array([r[2] for r in sel]) * 1e3
         elems = sum(r[1] for r in sel)
-        span = max(r[3] for r in sel) - warm
+        span = max(r[3] for r in sel) - lo
         return {"requests": len(sel), "throughput_lde_elems_per_s": elems / span,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_batch": float(np.mean([r[4] for r in sel]))}
 
+    def check(caps):
+        sel = [i for i in golden if i in caps]
+        bad = [i for i in sel if not np.array_equal(
+            caps[i], np.array([[int(w, 16) for w in row] for row in golden[i]["cap"]], dtype=np.uint64))]
+        return {"golden": "caps_serve.json", "matched": len(sel) - len(bad), "of": len(sel), "mismatched": bad[:10],
+                "bit_exact": not bad}
+
     warm = min(10.0, args.serve_seconds / 4)
-    cb_rows, cb_stats = run(args.serve_slots, args.serve_max_batch, reqs, True)
-    print("serve: continuous batching done", file=sys.stderr, flush=True)
-    fifo_rows, _ = run(1, 1, reqs, True)
-    print("serve: fifo done", file=sys.stderr, flush=True)
+    cb_rows, cb_stats, cb_caps = run(args.serve_slots, args.serve_max_batch, reqs, True, "continuous batching")
+    fifo_rows, fifo_stats, fifo_caps = run(1, 1, reqs, True, "fifo")
     sat = reqs[: args.serve_saturation]
-    sat_cb, _ = run(args.serve_slots, args.serve_max_batch, sat, False)
-    sat_fifo, _ = run(1, 1, sat, False)
-    print("serve: saturation done", file=sys.stderr, flush=True)
+    sat_cb, _, _ = run(args.serve_slots, args.serve_max_batch, sat, False, "saturation continuous batching")
+    sat_fifo, _, _ = run(1, 1, sat, False, "saturation fifo")
     sat_elems = sum(r[1] for r in sat_cb)
     cb = summarize(cb_rows, warm)
     fifo = summarize(fifo_rows, warm)
@@ -567,17 +719,23 @@ def serve_main(args):
         "config": {"workload": f"{SERVE_WORKLOAD}: Poisson {args.serve_rate}/s for {args.serve_seconds}s, 95% batch-mix "
                                "jobs (log rows 10..18, cols 20..135, cap 2) + 5% 80x2^18 jobs (cap 4), blowup 8, "
                                f"64 GiB admission budget, {args.serve_slots} slots, max batch {args.serve_max_batch}; "
-                               f"stats over arrivals after {warm:.0f}s; latency from arrival stamp to cap on host "
-                               "including trace upload from pinned memory",
+                               f"request i commits trace(seed 5, trace i); stats over arrivals after {warm:.0f}s; "
+                               "latency from arrival stamp to cap on host including trace upload from pinned memory",
                    "requests": len(reqs)},
         "latency_ms": {"p50": cb["p50_ms"], "p99": cb["p99_ms"]},
         "continuous_batching": cb,
+        "continuous_batching_warmup": summarize(cb_rows, 0.0, warm),
         "fifo_one_at_a_time": fifo,
+        "cb_over_fifo_p99": fifo["p99_ms"] / cb["p99_ms"],
         "saturation": {"requests": len(sat),
                        "continuous_batching_lde_elems_per_s": sat_elems / max(r[3] for r in sat_cb),
                        "fifo_lde_elems_per_s": sat_elems / max(r[3] for r in sat_fifo)},
         "server_stats": cb_stats,
+        "peak_admitted_GiB": cb_stats["hbm_peak"] / 2**30,
+        "cap_check": {"continuous_batching": check(cb_caps), "fifo": check(fifo_caps)},
     }
+    out["saturation"]["cb_over_fifo"] = (out["saturation"]["continuous_batching_lde_elems_per_s"]
+                                         / out["saturation"]["fifo_lde_elems_per_s"])
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -622,12 +780,23 @@ def main():
     torch.cuda.set_device(dev)
 
     ctx = v3db.Context(0)
-    trace = v3db.to_device(inputs.trace(seed, 0, C, L), dev)
+    stream = torch.cuda.current_stream(dev)
+    # a0: the trace is uploaded from pinned host memory once, timed apart from the commit
+    host = torch.from_numpy(inputs.trace(seed, 0, C, L).view(np.int64)).pin_memory()
+    trace = torch.empty((C, n), dtype=torch.int64, device=dev)
+    h2d_ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        trace.copy_(host, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2d_ms.append(e0.elapsed_time(e1))
+    del host
     lde = torch.empty((C, N), dtype=torch.int64, device=dev)
     tree = torch.empty((2 * N - (1 << h), 4), dtype=torch.int64, device=dev)
     cap = torch.empty((1 << h, 4), dtype=torch.int64, device=dev)
     job = v3db.Job(trace=trace, log_blowup=b, cap_height=h, shift=7, layout=layout, lde=lde, tree=tree, cap=cap)
-    stream = torch.cuda.current_stream(dev)
     default_schedule = schedule_json(ctx.get_schedule(L, b))
     schedule = default_schedule if args.no_autotune else schedule_json(ctx.autotune_lde(L, b, C, layout))
 
@@ -647,6 +816,7 @@ def main():
     wall = time.perf_counter() - t0
     phases = ctx.profile_read()
     ctx.profile_enable(False)
+    cap_host = v3db.to_host(cap)
 
     step_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)])
     elems = C * N
@@ -661,6 +831,8 @@ def main():
     lde_gbs = elems * LDE_BYTES_PER_ELEMENT / lde_avg_s / 1e9
     mk_avg_s = mk_ms / max(mk_n, 1) / 1e3
     perms_merkle = N - (1 << h)
+    leaf_kernel = "k_leaf_hash_mf" if ctx.hash_path == "mfma" else "k_leaf_hash"
+    h2d = float(np.median(h2d_ms))
 
     out = {
         "metric": METRIC,
@@ -683,26 +855,41 @@ def main():
             "poseidon_permutations_per_step": perms_leaf + perms_merkle,
         },
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "min": float(step_ms.min()), "max": float(step_ms.max())},
+                       "p50_ci95": median_ci95(step_ms), "min": float(step_ms.min()), "max": float(step_ms.max())},
         "trace_elements_per_s": C * n * args.steps / wall,
+        "h2d": {"what": "trace upload from pinned host memory (not in the timed step)", "bytes": C * n * 8,
+                "ms": h2d, "GBps": C * n * 8 / h2d / 1e6},
         "lde_schedule": {"used": schedule, "default": default_schedule,
                          "autotuned": not args.no_autotune},
-        "roofline": hash_roofline("k_leaf_hash_mf" if ctx.hash_path == "mfma" else "k_leaf_hash", perms_leaf,
+        "roofline": hash_roofline(leaf_kernel, perms_leaf,
                                   leaf_avg_s, ctx.hash_path, args.workload,
                                   {"algorithmic_bytes": elems * 8 + N * 32, "avg_launch_ms": leaf_avg_s * 1e3,
+                                   "launches_timed": leaf_n,
                                    "what": "rate-8 Poseidon sponge over every extended row"}),
         "phases": {
             "lde": {"avg_ms": lde_avg_s * 1e3, "bound": "hbm", "achieved_GBps": lde_gbs, "peak_GBps": HBM_PEAK_GBS,
-                    "frac": lde_gbs / HBM_PEAK_GBS, "algorithmic_bytes": elems * LDE_BYTES_PER_ELEMENT},
+                    "frac": lde_gbs / HBM_PEAK_GBS, "algorithmic_bytes": elems * LDE_BYTES_PER_ELEMENT,
+                    "traffic": measured_traffic("lde_passes", args.workload)},
             "leaf": {"avg_ms": leaf_avg_s * 1e3, "permutations": perms_leaf,
                      "permutations_per_s": perms_leaf / leaf_avg_s},
             "merkle": {"avg_ms": mk_avg_s * 1e3, "permutations": perms_merkle,
                        "permutations_per_s": perms_merkle / mk_avg_s if mk_avg_s else None},
         },
+        "cap_check": golden_check(args.workload, [cap_host]),
     }
     ctx.close()
+    del job, trace, lde, tree, cap
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        bt = batch_measure(args, max(4, args.steps // 2), 2)
+        out["batch"] = {k: bt[k] for k in ("value", "unit", "ms_per_step", "latency_ms", "one_launch_per_trace",
+                                           "batched_over_per_trace", "lde_schedules")}
+        out["batch"]["workload"] = bt["config"]["workload"]
+        out["batch"]["lde_elements_per_step"] = bt["config"]["lde_elements_per_step"]
+        out["batch"]["cap_check"] = bt["cap_check"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(C, b, h, layout, min(args.cpu_sample_log_rows, L))
+        out["cpu_baseline"] = cpu_baseline(C, b, h, layout, min(args.cpu_sample_log_rows, L),
+                                           min(args.cpu_sample_log_rows_1t, L))
     print(json.dumps(out), flush=True)
 
 

@@ -152,16 +152,22 @@ typedef struct {
   uint64_t *d_cap;  /* [2^cap_height][4], device; required */
 } v3db_commit_job;
 
-/* Commit many independent traces of different shapes. Natural-layout jobs are
- * committed together, phase by phase: every phase (each extension pass,
- * leaf hashing, each tree depth) runs as one launch over the work of all jobs,
- * so small traces share the GPU. The launch sequence for a given list of shapes
- * (per stream) is captured once as a HIP graph and replayed; only a small table
- * of buffer pointers is uploaded per call. Bit-reversed jobs are committed one
- * at a time. Scratch for NULL d_lde/d_tree comes from the context (per stream)
- * and counts against its HBM budget. Results are identical to committing each
- * job alone. Errors: as v3db_lde / v3db_merkle_commit for any job (checked
- * before anything is enqueued), OUT_OF_MEMORY if the scratch does not fit. */
+/* Commit many independent traces of different shapes: the proof backend answers
+ * challenges on demand (§3.1, paragraph "Proving backend (online/audit)"), so many
+ * proofs, hence many trace commitments (comm = MerkleTree over Hash = Poseidon of
+ * the extended rows, §4.3 "Snapshot Commitments"), are in flight at once.
+ * Natural-layout jobs are committed together, phase by phase: every phase (each
+ * extension pass, leaf hashing, each tree depth) runs as one launch over the work of
+ * all jobs, so small traces share the GPU. A list of shapes seen for the first time
+ * (per stream) is launched directly; from its second call on, its launch sequence is
+ * captured once as a HIP graph and replayed, and only a small table of buffer
+ * pointers is uploaded per call. Bit-reversed jobs are committed one at a time.
+ * Scratch for NULL d_lde/d_tree comes from the context (per stream) and counts
+ * against its HBM budget. Results are identical to committing each job alone.
+ * jobs is a host array of n_jobs descriptors (read during the call only); every
+ * buffer in it is the caller's and must stay alive until the stream reaches this
+ * point. Errors: as v3db_lde / v3db_merkle_commit for any job (checked before
+ * anything is enqueued), OUT_OF_MEMORY if the scratch does not fit. */
 v3db_status v3db_commit_batch(v3db_ctx *ctx, const v3db_commit_job *jobs, size_t n_jobs, v3db_stream stream);
 
 /* Phase timing. While enabled, commit calls record HIP events on their stream
@@ -352,15 +358,21 @@ v3db_status v3db_schedules_load(v3db_ctx *ctx, const char *path, size_t *count);
 size_t v3db_commit_batch_scratch_bytes(const v3db_commit_job *jobs, size_t n_jobs);
 
 /* ---------------------------------------------------------------- serving
- * An audit-on-demand commit server: requests (host traces) arrive at any time;
- * a scheduler thread admits them in arrival order whenever a slot (a stream) and
- * enough of the server's HBM budget are free, as many as fit into one batch, and
- * runs each batch on its slot stream: trace upload, one v3db_commit_batch, cap
- * download. Batches on different slots overlap on the device; a request that
- * arrives while others run is admitted as soon as a slot and memory free up.
- * All request buffers (trace, LDE, tree, cap) and batch scratch live in one
- * device arena of the budget's size, reserved at creation and kept resident;
- * a request is admitted when its buffers fit in the arena. */
+ * An audit-on-demand commit server (§3.1, paragraph "Proving backend (online/audit)":
+ * proofs are produced when a returned result is challenged, so commitment work
+ * arrives as requests at any time; each request is one trace commitment as in §4.3).
+ * Requests (host traces) arrive at any time; a scheduler thread admits them in
+ * arrival order whenever a slot (a stream) and enough of the server's HBM budget are
+ * free, as many as fit into one batch, and runs each batch on its slot stream: trace
+ * upload, one v3db_commit_batch, cap download. Batches on different slots overlap on
+ * the device; a request that arrives while others run is admitted as soon as a slot
+ * and memory free up. All request buffers (trace, LDE, tree, cap) and batch scratch
+ * live in one device arena of the budget's size, reserved at creation and kept
+ * resident; a request is admitted when its buffers fit in the arena.
+ * Requests carry host traces and receive host caps (v3db_request) rather than device
+ * job descriptors: the server owns where a request's device buffers live (its arena,
+ * which is what admission by HBM budget manages), and a request's latency runs from its
+ * arrival to its cap on the host, the trace upload included. */
 typedef struct {
   uint32_t slots;             /* batches in flight at once (streams), >= 1 */
   uint32_t max_batch;         /* requests per batch, 0 = no limit */
@@ -386,6 +398,10 @@ typedef struct {
   double t_arrive, t_admit, t_done; /* v3db_clock() seconds; latency = t_done - t_arrive */
   uint32_t batch_size;              /* requests in the batch it ran in */
   uint32_t slot;
+  /* device time of its batch (trace upload to cap download) in seconds since the server
+   * was created, from events on the slot's stream; -1 when not measured (simulated
+   * executor, failed batch) */
+  double t_dev_start, t_dev_end;
 } v3db_request_timing;
 
 typedef struct {

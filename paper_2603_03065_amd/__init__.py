@@ -84,6 +84,8 @@ class _Timing(ctypes.Structure):
         ("t_done", ctypes.c_double),
         ("batch_size", ctypes.c_uint32),
         ("slot", ctypes.c_uint32),
+        ("t_dev_start", ctypes.c_double),
+        ("t_dev_end", ctypes.c_double),
     ]
 
 
@@ -211,11 +213,19 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-def _ptr(t) -> Optional[int]:
+def _ptr(t, numel: Optional[int] = None, device=None, what: str = "tensor") -> Optional[int]:
+    """Device pointer of a contiguous int64 CUDA tensor; with numel, the tensor must hold at
+    least that many words, and with device, live on that device (the library writes through
+    raw pointers, so a short or misplaced buffer is refused here)."""
     if t is None:
         return None
     import torch
-    assert t.dtype == torch.int64 and t.is_cuda and t.is_contiguous(), "expected a contiguous int64 CUDA tensor"
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous int64 CUDA tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what}: holds {t.numel()} words, needs {numel}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: on cuda:{t.device.index}, the context is on cuda:{device}")
     return t.data_ptr()
 
 
@@ -306,14 +316,16 @@ class Context:
             raise ValueError("rows must be a power of two")
         if out is None:
             out = torch.empty((n_cols, n << log_blowup), dtype=torch.int64, device=trace.device)
-        _check(lib().v3db_lde(self._h, _ptr(trace), n_cols, log_rows, log_blowup, shift, layout, _ptr(out),
-                              _stream(stream)))
+        d = self.device
+        _check(lib().v3db_lde(self._h, _ptr(trace, n_cols * n, d, "trace"), n_cols, log_rows, log_blowup, shift,
+                              layout, _ptr(out, (n_cols * n) << log_blowup, d, "out"), _stream(stream)))
         return out
 
     def poseidon_permute(self, states, stream=None):
         """In place on a [count][12] tensor."""
         count = states.numel() // 12
-        _check(lib().v3db_poseidon_permute(self._h, _ptr(states), count, _stream(stream)))
+        _check(lib().v3db_poseidon_permute(self._h, _ptr(states, 12 * count, self.device, "states"), count,
+                                           _stream(stream)))
         return states
 
     def merkle_commit(self, mat, cap_height: int, tree=None, cap=None, stream=None):
@@ -324,7 +336,11 @@ class Context:
             raise ValueError("leaf count must be a power of two")
         if cap is None:
             cap = torch.empty((1 << cap_height, 4), dtype=torch.int64, device=mat.device)
-        _check(lib().v3db_merkle_commit(self._h, _ptr(mat), n_cols, log_leaves, cap_height, _ptr(tree), _ptr(cap),
+        d = self.device
+        tree_words = ((2 << log_leaves) - (1 << cap_height)) * 4 if cap_height <= log_leaves else None
+        _check(lib().v3db_merkle_commit(self._h, _ptr(mat, n_cols * nl, d, "mat"), n_cols, log_leaves, cap_height,
+                                        _ptr(tree, tree_words, d, "tree"),
+                                        _ptr(cap, (1 << cap_height) * 4 if cap_height < 63 else None, d, "cap"),
                                         _stream(stream)))
         return cap
 
@@ -338,9 +354,15 @@ class Context:
         if rows is None:
             rows = torch.empty((q, n_cols), dtype=torch.int64, device=mat.device)
         if paths is None:
-            paths = torch.empty((q, log_leaves - cap_height, 4), dtype=torch.int64, device=mat.device)
-        _check(lib().v3db_open_batch(self._h, _ptr(mat), n_cols, log_leaves, _ptr(tree), cap_height, _ptr(idx), q,
-                                     _ptr(rows), _ptr(paths) if paths.numel() else None, _stream(stream)))
+            paths = torch.empty((q, max(log_leaves - cap_height, 0), 4), dtype=torch.int64, device=mat.device)
+        d = self.device
+        depth = max(log_leaves - cap_height, 0)
+        tree_words = ((2 << log_leaves) - (1 << cap_height)) * 4 if cap_height <= log_leaves else None
+        _check(lib().v3db_open_batch(self._h, _ptr(mat, n_cols * nl, d, "mat"), n_cols, log_leaves,
+                                     _ptr(tree, tree_words, d, "tree"), cap_height, _ptr(idx, q, d, "idx"), q,
+                                     _ptr(rows, q * n_cols, d, "rows"),
+                                     _ptr(paths, q * depth * 4, d, "paths") if paths.numel() else None,
+                                     _stream(stream)))
         return rows, paths
 
     def verify_batch(self, rows, paths, idx, cap, log_leaves: int, cap_height: int, ok=None, stream=None):
@@ -349,10 +371,15 @@ class Context:
         q, n_cols = rows.shape
         if ok is None:
             ok = torch.empty((q,), dtype=torch.int32, device=rows.device)
-        assert ok.dtype == torch.int32 and ok.is_cuda and ok.is_contiguous()
-        _check(lib().v3db_verify_batch(self._h, _ptr(rows), n_cols, log_leaves, cap_height, _ptr(idx), q,
-                                       _ptr(paths) if paths.numel() else None, _ptr(cap), ok.data_ptr(),
-                                       _stream(stream)))
+        if ok.dtype != torch.int32 or not ok.is_cuda or not ok.is_contiguous() or ok.numel() < q:
+            raise ValueError(f"ok: expected a contiguous int32 CUDA tensor of at least {q} entries")
+        d = self.device
+        depth = max(log_leaves - cap_height, 0)
+        _check(lib().v3db_verify_batch(self._h, _ptr(rows, q * n_cols, d, "rows"), n_cols, log_leaves, cap_height,
+                                       _ptr(idx, q, d, "idx"), q,
+                                       _ptr(paths, q * depth * 4, d, "paths") if paths.numel() else None,
+                                       _ptr(cap, (1 << cap_height) * 4 if cap_height < 63 else None, d, "cap"),
+                                       ok.data_ptr(), _stream(stream)))
         return ok
 
     def snapshot_commit(self, log_lists: int, log_slots: int, m: int, dim: int, k: int, flag, item, codes,
@@ -366,10 +393,19 @@ class Context:
             list_roots = torch.empty((1 << log_lists, 4), dtype=torch.int64, device=dev)
         mk = torch.empty((4,), dtype=torch.int64, device=dev)
         cb = torch.empty((4,), dtype=torch.int64, device=dev)
-        sn = _Snapshot(log_lists, log_slots, m, dim, k, _ptr(flag), _ptr(item), _ptr(codes), _ptr(centroids),
-                       _ptr(codebooks))
-        _check(lib().v3db_snapshot_commit(self._h, ctypes.byref(sn), _ptr(list_roots), _ptr(mk), _ptr(cb),
-                                          _stream(stream)))
+        d = self.device
+        # sizes are checked for shapes the library accepts; it reports the others itself
+        valid = m >= 1 and k >= 1 and dim >= 1 and dim % m == 0 and log_lists + log_slots <= 26 and m <= 65535 \
+            and k * dim < 1 << 32
+        N, nl = (1 << (log_lists + log_slots), 1 << log_lists) if valid else (None, None)
+        need = (lambda x: x) if valid else (lambda x: None)
+        sn = _Snapshot(log_lists, log_slots, m, dim, k, _ptr(flag, need(N), d, "flag"), _ptr(item, need(N), d, "item"),
+                       _ptr(codes, need(m * N if valid else 0), d, "codes"),
+                       _ptr(centroids, need(nl * dim if valid else 0), d, "centroids"),
+                       _ptr(codebooks, need(k * dim), d, "codebooks"))
+        _check(lib().v3db_snapshot_commit(self._h, ctypes.byref(sn), _ptr(list_roots, need(4 * nl if valid else 0), d,
+                                                                          "list_roots"),
+                                          _ptr(mk), _ptr(cb), _stream(stream)))
         return mk, cb, list_roots
 
     def grand_product(self, cols, alpha: int, beta: int, z=None, want_z: bool = True, stream=None):
@@ -380,8 +416,10 @@ class Context:
         if want_z and z is None:
             z = torch.empty((n,), dtype=torch.int64, device=cols.device)
         total = torch.empty((1,), dtype=torch.int64, device=cols.device)
-        _check(lib().v3db_grand_product(self._h, _ptr(cols) if n else None, width, n, alpha % P, beta % P,
-                                        _ptr(z) if (want_z and n) else None, _ptr(total), _stream(stream)))
+        d = self.device
+        _check(lib().v3db_grand_product(self._h, _ptr(cols, width * n, d, "cols") if n else None, width, n, alpha % P,
+                                        beta % P, _ptr(z, n, d, "z") if (want_z and n) else None,
+                                        _ptr(total, 1, d, "total"), _stream(stream)))
         return (z if want_z else None), total
 
     def fri_commit(self, codeword, shift: int, betas, cap_height: int, folded=None, trees=None, caps=None,
@@ -402,12 +440,18 @@ class Context:
         if want_trees and trees is None:
             words = sum(((n >> r) - (1 << cap_height)) * 4 for r in range(rounds))
             trees = torch.empty((words,), dtype=torch.int64, device=dev)
-        _check(lib().v3db_fri_commit(self._h, _ptr(codeword), log_n, shift, b.ctypes.data, rounds, cap_height,
-                                     _ptr(folded), _ptr(trees), _ptr(caps), _stream(stream)))
+        d = self.device
+        ok = rounds <= log_n and cap_height < 63
+        _check(lib().v3db_fri_commit(self._h, _ptr(codeword, n, d, "codeword"), log_n, shift, b.ctypes.data, rounds,
+                                     cap_height, _ptr(folded, n - (n >> rounds) if ok else None, d, "folded"),
+                                     _ptr(trees, sum(((n >> r) - (1 << cap_height)) * 4 for r in range(rounds))
+                                          if ok and cap_height + rounds <= log_n else None, d, "trees"),
+                                     _ptr(caps, rounds * (1 << cap_height) * 4 if ok else None, d, "caps"),
+                                     _stream(stream)))
         return folded, caps, trees
 
     @staticmethod
-    def _jobs(jobs: Sequence[Job]):
+    def _jobs(jobs: Sequence[Job], device=None):
         import torch
         arr = (_Job * len(jobs))()
         for i, j in enumerate(jobs):
@@ -417,12 +461,18 @@ class Context:
                 raise ValueError("rows must be a power of two")
             if j.cap is None:
                 j.cap = torch.empty((1 << j.cap_height, 4), dtype=torch.int64, device=j.trace.device)
-            arr[i] = _Job(_ptr(j.trace), n_cols, log_rows, j.log_blowup, j.cap_height, j.shift, j.layout,
-                          _ptr(j.lde), _ptr(j.tree), _ptr(j.cap))
+            logN = log_rows + j.log_blowup
+            ok = 0 <= j.cap_height <= logN < 63
+            arr[i] = _Job(_ptr(j.trace, n_cols * n, device, f"job {i} trace"), n_cols, log_rows, j.log_blowup,
+                          j.cap_height, j.shift, j.layout,
+                          _ptr(j.lde, n_cols << logN if ok else None, device, f"job {i} lde"),
+                          _ptr(j.tree, ((2 << logN) - (1 << j.cap_height)) * 4 if ok else None, device,
+                               f"job {i} tree"),
+                          _ptr(j.cap, (1 << j.cap_height) * 4 if ok else None, device, f"job {i} cap"))
         return arr
 
     def commit_batch(self, jobs: Sequence[Job], stream=None):
-        arr = self._jobs(jobs)
+        arr = self._jobs(jobs, self.device)
         _check(lib().v3db_commit_batch(self._h, arr, len(jobs), _stream(stream)))
         return [j.cap for j in jobs]
 
@@ -527,7 +577,8 @@ class Server:
             return None
         _, cap = self._keep.pop(ticket)
         timing = {"t_arrive": t.t_arrive, "t_admit": t.t_admit, "t_done": t.t_done,
-                  "batch_size": int(t.batch_size), "slot": int(t.slot)}
+                  "batch_size": int(t.batch_size), "slot": int(t.slot),
+                  "t_dev_start": t.t_dev_start, "t_dev_end": t.t_dev_end}
         return int(st.value), cap, timing
 
     def drain(self):

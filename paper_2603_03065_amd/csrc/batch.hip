@@ -374,21 +374,46 @@ struct BatchGraph {
   size_t table_bytes = 0, jobs_bytes = 0;
   void *h_table = nullptr;      // pinned staging copy
   hipEvent_t staged = nullptr;  // the last upload from h_table has been read
+  hipEvent_t done = nullptr;    // the last launch of the graph has finished
   uint64_t last_use = 0;
+};
+
+// The table of batches launched without a graph on one stream: kept and reused (grown
+// only when a batch's table is larger), so such batches allocate nothing once it has
+// reached its working size.
+struct EagerTable {
+  hipStream_t stream = nullptr;
+  void *d = nullptr, *h = nullptr;
+  size_t bytes = 0;
+  hipEvent_t staged = nullptr;  // the last upload from h has been read
+  hipEvent_t done = nullptr;    // the last batch's kernels have finished reading d
 };
 
 static void destroy_graph(v3db_ctx *ctx, BatchGraph *g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->staged) (void)hipEventDestroy(g->staged);
+  if (g->done) (void)hipEventDestroy(g->done);
   if (g->h_table) (void)hipHostFree(g->h_table);
   if (g->d_table) ctx_free(ctx, g->d_table, g->table_bytes);
   delete g;
 }
 
+static void free_eager_table(v3db_ctx *ctx, EagerTable *t) {
+  if (t->staged) (void)hipEventDestroy(t->staged);
+  if (t->done) (void)hipEventDestroy(t->done);
+  if (t->h) (void)hipHostFree(t->h);
+  if (t->d) ctx_free(ctx, t->d, t->bytes);
+  delete t;
+}
+
+// Callers have waited for the device (context teardown, schedule changes).
 void free_batch_graphs(v3db_ctx *ctx) {
   for (BatchGraph *g : ctx->graphs) destroy_graph(ctx, g);
   ctx->graphs.clear();
+  for (EagerTable *t : ctx->eager_tables) free_eager_table(ctx, t);
+  ctx->eager_tables.clear();
+  ctx->seen_keys.clear();
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   ctx->capture_stream = nullptr;
 }
@@ -447,49 +472,68 @@ v3db_status capture_group(v3db_ctx *ctx, const GroupPlan &g, BatchGraph *bg) {
   return hip_check(e, "capture batch graph");
 }
 
-// Commit a group of natural-layout jobs together; scratch holds
-// batched_scratch() of every job, in order.
-v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs, uint8_t *scratch,
-                         hipStream_t s) {
-  const size_t nj = jobs.size();
-  std::vector<const LdePlan *> plans(nj);
-  for (size_t i = 0; i < nj; i++) {
-    v3db_status st = get_plan(ctx, jobs[i].log_rows, jobs[i].log_blowup, jobs[i].shift, &plans[i]);
+// Launch the phases of a group without a graph, with the job and range table staged
+// through the stream's own reusable table.
+v3db_status launch_eager(v3db_ctx *ctx, const GroupPlan &gp, const std::vector<BJob> &bj, hipStream_t s) {
+  const size_t jobs_bytes = (bj.size() * sizeof(BJob) + 255) & ~size_t(255);
+  const size_t bytes = jobs_bytes + gp.ranges.size() * sizeof(BRange);
+  EagerTable *t = nullptr;
+  for (EagerTable *x : ctx->eager_tables)
+    if (x->stream == s) t = x;
+  hipError_t e = hipSuccess;
+  if (!t) {
+    t = new EagerTable();
+    t->stream = s;
+    e = hipEventCreateWithFlags(&t->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      free_eager_table(ctx, t);
+      return hip_check(e, "batch table events");
+    }
+    ctx->eager_tables.push_back(t);
+  }
+  // the last upload from the staging copy must have been read before it is rewritten
+  e = hipEventSynchronize(t->staged);
+  if (e != hipSuccess) return hip_check(e, "batch staging wait");
+  if (bytes > t->bytes) {
+    // grow (rarely: the first size covers batches of dozens of jobs) once the kernels
+    // still reading the old table are done
+    e = hipEventSynchronize(t->done);
+    if (e != hipSuccess) return hip_check(e, "batch table wait");
+    if (t->h) (void)hipHostFree(t->h);
+    if (t->d) ctx_free(ctx, t->d, t->bytes);
+    t->h = t->d = nullptr;
+    t->bytes = 0;
+    const size_t want = std::max(bytes, size_t(256) << 10);
+    v3db_status st = ctx_alloc(ctx, &t->d, want, "batch tables");
     if (st != V3DB_OK) return st;
-  }
-  const std::vector<uint64_t> key = shape_key(jobs, s);
-  BatchGraph *bg = nullptr;
-  for (BatchGraph *g : ctx->graphs)
-    if (g->key == key) bg = g;
-  GroupPlan gp;
-  plan_group(plans, jobs, gp);
-  if (!bg) {
-    if (ctx->graphs.size() >= 8) {  // evict the least recently used
-      auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
-                                 [](BatchGraph *a, BatchGraph *b) { return a->last_use < b->last_use; });
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return hip_check(e, "graph eviction sync");
-      destroy_graph(ctx, *it);
-      ctx->graphs.erase(it);
+    e = hipHostMalloc(&t->h, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ctx_free(ctx, t->d, want);
+      t->d = nullptr;
+      return hip_check(e, "batch staging");
     }
-    bg = new BatchGraph();
-    bg->key = key;
-    bg->jobs_bytes = (nj * sizeof(BJob) + 255) & ~size_t(255);
-    bg->table_bytes = bg->jobs_bytes + gp.ranges.size() * sizeof(BRange);
-    v3db_status st = ctx_alloc(ctx, &bg->d_table, bg->table_bytes, "batch tables");
-    hipError_t e = hipSuccess;
-    if (st == V3DB_OK) e = hipHostMalloc(&bg->h_table, bg->table_bytes, hipHostMallocDefault);
-    if (st == V3DB_OK && e == hipSuccess) e = hipEventCreateWithFlags(&bg->staged, hipEventDisableTiming);
-    if (st == V3DB_OK && e != hipSuccess) st = hip_check(e, "batch staging");
-    if (st == V3DB_OK) st = capture_group(ctx, gp, bg);
-    if (st != V3DB_OK) {
-      destroy_graph(ctx, bg);
-      return st;
-    }
-    ctx->graphs.push_back(bg);
+    t->bytes = want;
   }
-  bg->last_use = ++ctx->graph_clock;
-  // this call's buffers
+  memcpy(t->h, bj.data(), bj.size() * sizeof(BJob));
+  memcpy((uint8_t *)t->h + jobs_bytes, gp.ranges.data(), gp.ranges.size() * sizeof(BRange));
+  e = hipMemcpyAsync(t->d, t->h, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(t->staged, s);
+  if (e != hipSuccess) return hip_check(e, "batch table upload");
+  hipEvent_t e0 = prof_mark(ctx, s);
+  launch_phases(ctx, gp, (const BJob *)t->d, (const BRange *)((uint8_t *)t->d + jobs_bytes), s);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(t->done, s);
+  if (e != hipSuccess) return hip_check(e, "batch launch");
+  hipEvent_t e1 = prof_mark(ctx, s);
+  prof_interval(ctx, V3DB_PHASE_BATCH, e0, e1);
+  return V3DB_OK;
+}
+
+// The job descriptors of a group for this call's buffers.
+std::vector<BJob> group_jobs(const std::vector<const LdePlan *> &plans, const std::vector<v3db_commit_job> &jobs,
+                             uint8_t *scratch) {
+  const size_t nj = jobs.size();
   std::vector<BJob> bj(nj);
   uint8_t *p = scratch;
   for (size_t i = 0; i < nj; i++) {
@@ -513,6 +557,62 @@ v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs
     b.cap_height = j.cap_height;
     b.pad = 0;
   }
+  return bj;
+}
+
+// Commit a group of natural-layout jobs together; scratch holds
+// batched_scratch() of every job, in order. A list of shapes seen for the first time
+// is launched directly (a server's batches rarely repeat); from its second call on it
+// is captured as a graph and replayed.
+v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs, uint8_t *scratch,
+                         hipStream_t s) {
+  const size_t nj = jobs.size();
+  std::vector<const LdePlan *> plans(nj);
+  for (size_t i = 0; i < nj; i++) {
+    v3db_status st = get_plan(ctx, jobs[i].log_rows, jobs[i].log_blowup, jobs[i].shift, &plans[i]);
+    if (st != V3DB_OK) return st;
+  }
+  const std::vector<uint64_t> key = shape_key(jobs, s);
+  BatchGraph *bg = nullptr;
+  for (BatchGraph *g : ctx->graphs)
+    if (g->key == key) bg = g;
+  GroupPlan gp;
+  plan_group(plans, jobs, gp);
+  const std::vector<BJob> bj = group_jobs(plans, jobs, scratch);
+  if (!bg) {
+    auto seen = std::find(ctx->seen_keys.begin(), ctx->seen_keys.end(), key);
+    if (seen == ctx->seen_keys.end()) {
+      if (ctx->seen_keys.size() >= 64) ctx->seen_keys.erase(ctx->seen_keys.begin());
+      ctx->seen_keys.push_back(key);
+      return launch_eager(ctx, gp, bj, s);
+    }
+    ctx->seen_keys.erase(seen);
+    if (ctx->graphs.size() >= 8) {  // evict the least recently used, once its last launch is done
+      auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                 [](BatchGraph *a, BatchGraph *b) { return a->last_use < b->last_use; });
+      hipError_t e = hipEventSynchronize((*it)->done);
+      if (e != hipSuccess) return hip_check(e, "graph eviction wait");
+      destroy_graph(ctx, *it);
+      ctx->graphs.erase(it);
+    }
+    bg = new BatchGraph();
+    bg->key = key;
+    bg->jobs_bytes = (nj * sizeof(BJob) + 255) & ~size_t(255);
+    bg->table_bytes = bg->jobs_bytes + gp.ranges.size() * sizeof(BRange);
+    v3db_status st = ctx_alloc(ctx, &bg->d_table, bg->table_bytes, "batch tables");
+    hipError_t e = hipSuccess;
+    if (st == V3DB_OK) e = hipHostMalloc(&bg->h_table, bg->table_bytes, hipHostMallocDefault);
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventCreateWithFlags(&bg->staged, hipEventDisableTiming);
+    if (st == V3DB_OK && e == hipSuccess) e = hipEventCreateWithFlags(&bg->done, hipEventDisableTiming);
+    if (st == V3DB_OK && e != hipSuccess) st = hip_check(e, "batch staging");
+    if (st == V3DB_OK) st = capture_group(ctx, gp, bg);
+    if (st != V3DB_OK) {
+      destroy_graph(ctx, bg);
+      return st;
+    }
+    ctx->graphs.push_back(bg);
+  }
+  bg->last_use = ++ctx->graph_clock;
   // the previous upload from the staging buffer must have been read before it is rewritten
   hipError_t e = hipEventSynchronize(bg->staged);
   if (e != hipSuccess) return hip_check(e, "batch staging wait");
@@ -523,6 +623,7 @@ v3db_status commit_group(v3db_ctx *ctx, const std::vector<v3db_commit_job> &jobs
   if (e != hipSuccess) return hip_check(e, "batch table upload");
   hipEvent_t e0 = prof_mark(ctx, s);
   e = hipGraphLaunch(bg->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(bg->done, s);
   if (e != hipSuccess) return hip_check(e, "batch graph launch");
   hipEvent_t e1 = prof_mark(ctx, s);
   prof_interval(ctx, V3DB_PHASE_BATCH, e0, e1);

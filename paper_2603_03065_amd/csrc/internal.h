@@ -74,6 +74,7 @@ struct ScratchBuf {
 };
 
 struct BatchGraph;
+struct EagerTable;
 
 }  // namespace v3db
 
@@ -102,6 +103,10 @@ struct v3db_ctx {
   size_t batch_group_bytes = size_t(32) << 30;
   std::vector<v3db::BatchGraph *> graphs;
   uint64_t graph_clock = 0;
+  // shape lists seen once (a graph is captured at the second sighting) and, per
+  // stream, the job and range table of batches launched without a graph
+  std::vector<std::vector<uint64_t>> seen_keys;
+  std::vector<v3db::EagerTable *> eager_tables;
   hipStream_t capture_stream = nullptr;
   hipStream_t side_stream = nullptr;  // snapshot codebook digest, forked from and joined into the caller's stream
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;

@@ -34,6 +34,7 @@ struct Request {
   v3db_request req{};
   size_t footprint = 0;  // device bytes while admitted (buffers and its share of batch scratch)
   double t_arrive = 0, t_admit = -1, t_done = -1;
+  double t_dev_start = -1, t_dev_end = -1;  // device time of its batch (HIP executor)
   uint32_t batch_size = 0, slot = 0;
   v3db_status status = V3DB_OK;
   bool done = false;
@@ -183,7 +184,10 @@ class HipExecutor : public Executor {
  public:
   HipExecutor(v3db_ctx *ctx, size_t budget, int slots) : Executor(budget, slots), ctx_(ctx), st_(slots) {}
   ~HipExecutor() override {
+    if (ref_) (void)hipEventDestroy(ref_);
     for (auto &s : st_) {
+      if (s.t0) (void)hipEventDestroy(s.t0);
+      if (s.t1) (void)hipEventDestroy(s.t1);
       if (s.ev) (void)hipEventDestroy(s.ev);
       if (s.stream) (void)hipStreamDestroy(s.stream);
       if (s.h_caps) (void)hipHostFree(s.h_caps);
@@ -201,9 +205,15 @@ class HipExecutor : public Executor {
     for (auto &s : st_) {
       e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreate(&s.t0);
+      if (e == hipSuccess) e = hipEventCreate(&s.t1);
       if (e != hipSuccess) return hip_check(e, "server slot");
     }
-    return V3DB_OK;
+    // the origin of the batches' device times
+    e = hipEventCreate(&ref_);
+    if (e == hipSuccess) e = hipEventRecord(ref_, st_[0].stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ref_);
+    return hip_check(e, "server reference event");
   }
   v3db_status launch(int slot, std::vector<Request *> &batch) override {
     (void)hipSetDevice(ctx_->device);
@@ -222,6 +232,8 @@ class HipExecutor : public Executor {
     }
     std::vector<v3db_commit_job> jobs;
     jobs.reserve(batch.size());
+    hipError_t e0 = hipEventRecord(s.t0, s.stream);
+    if (e0 != hipSuccess) return fail(s, e0, "server: batch start event");
     for (Request *r : batch) {
       const v3db_request &q = r->req;
       hipError_t e = hipMemcpyAsync(ptr(r, 0), q.h_trace, r->len[0], hipMemcpyHostToDevice, s.stream);
@@ -251,7 +263,8 @@ class HipExecutor : public Executor {
       if (e != hipSuccess) return fail(s, e, "server: cap download");
       off += r->len[3] / 8;
     }
-    hipError_t e = hipEventRecord(s.ev, s.stream);
+    hipError_t e = hipEventRecord(s.t1, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.ev, s.stream);
     if (e != hipSuccess) return fail(s, e, "server: batch event");
     return V3DB_OK;
   }
@@ -260,9 +273,17 @@ class HipExecutor : public Executor {
     Slot &s = st_[slot];
     hipError_t e = hipEventSynchronize(s.ev);
     st = e == hipSuccess ? V3DB_OK : hip_check(e, "server: batch");
+    float ms0 = -1e3f, ms1 = -1e3f;
+    if (st == V3DB_OK && (hipEventElapsedTime(&ms0, ref_, s.t0) != hipSuccess ||
+                          hipEventElapsedTime(&ms1, ref_, s.t1) != hipSuccess)) {
+      (void)hipGetLastError();
+      ms0 = ms1 = -1e3f;
+    }
     size_t off = 0;
     for (Request *r : batch) {
       if (st == V3DB_OK) memcpy(r->req.h_cap, s.h_caps + off, r->len[3]);
+      r->t_dev_start = ms0 * 1e-3;
+      r->t_dev_end = ms1 * 1e-3;
       off += r->len[3] / 8;
     }
   }
@@ -271,6 +292,7 @@ class HipExecutor : public Executor {
   struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // timed: batch start and end on the slot's stream
     uint64_t *h_caps = nullptr;
     size_t h_caps_words = 0;
   };
@@ -282,6 +304,7 @@ class HipExecutor : public Executor {
   v3db_ctx *ctx_;
   std::vector<Slot> st_;
   uint8_t *base_ = nullptr;
+  hipEvent_t ref_ = nullptr;
 };
 
 // Models a device that needs ns_per_element per LDE element of a batch; batches
@@ -510,6 +533,8 @@ v3db_status v3db_server_poll(v3db_server *s, uint64_t ticket, int *done, v3db_st
     timing->t_done = r->t_done;
     timing->batch_size = r->batch_size;
     timing->slot = r->slot;
+    timing->t_dev_start = r->t_dev_start;
+    timing->t_dev_end = r->t_dev_end;
   }
   if (r->done) s->reqs.erase(it);
   return V3DB_OK;

@@ -145,3 +145,30 @@ def serve_checked(requests):
     sample (u < 0.02 on SERVE_SAMPLE_STREAM) and every 80 x 2^18 request."""
     return [i for i, (_, L, C, h) in enumerate(requests)
             if float(uniform01(SERVE_SAMPLE_STREAM, i)) < 0.02 or (L, C, h) == SERVE_BIG_SHAPE]
+
+
+# ---- the same traces drawn on a torch device ---------------------------------------
+
+def trace_torch(seed: int, trace_id: int, n_cols: int, log_rows: int, device="cuda", col0: int = 0):
+    """trace() drawn with torch int64 operations on `device` (same values, as the raw
+    bits of an int64 tensor [n_cols][2^log_rows]): for workloads too large to draw on
+    the host in time. int64 multiplication wraps modulo 2^64 like uint64, right shifts
+    are made logical by masking, and z >= p (as unsigned) is z in [p - 2^64, 0) as signed."""
+    import torch
+    assert log_rows <= 24 and col0 + n_cols <= (1 << 16)
+
+    def s64(x: int) -> int:
+        return x - (1 << 64) if x >= 1 << 63 else x
+
+    def srl(z, k: int):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    rows = torch.arange(1 << log_rows, dtype=torch.int64, device=device)
+    cols = torch.arange(col0, col0 + n_cols, dtype=torch.int64, device=device)
+    idx = (trace_id << 40) | (cols[:, None] << 24) | rows[None, :]
+    z = (idx + 1) * s64(0x9E3779B97F4A7C15) + s64(seed & ((1 << 64) - 1))
+    z = (z ^ srl(z, 30)) * s64(0xBF58476D1CE4E5B9)
+    z = (z ^ srl(z, 27)) * s64(0x94D049BB133111EB)
+    z = z ^ srl(z, 31)
+    big = (z < 0) & (z >= s64(P))
+    return torch.where(big, z - s64(P), z)

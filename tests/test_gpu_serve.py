@@ -56,3 +56,30 @@ def test_server_isolates_an_injected_failure(v3db):
             ctx.commit(job)
             torch.cuda.synchronize()
             assert np.array_equal(res[k][1], v3db.to_host(job.cap))
+
+
+def test_batches_on_different_slots_overlap_on_the_device(v3db):
+    """The first 48 requests of the serving workload (its shape mix: log rows 10..18,
+    20..135 columns, some 80 x 2^18), all queued at once into a 4-slot server: the
+    device intervals (events on each slot's stream, upload to cap download) of batches
+    on different slots overlap, and each cap equals the one the trace gets alone."""
+    import torch
+    reqs = inputs.serve_requests(120.0, 50.0)[:48]
+    hosts = [inputs.trace_torch(inputs.SERVE_TRACE_SEED, i, C, L, device="cuda").cpu().pin_memory()
+             for i, (_, L, C, h) in enumerate(reqs)]
+    with v3db.Context(0) as ctx:
+        with v3db.Server(ctx, slots=4, hbm_budget=64 << 30, max_batch=4) as srv:
+            tickets = [srv.submit(hst, cap_height=h) for hst, (_, L, C, h) in zip(hosts, reqs)]
+            srv.drain()
+            res = [srv.poll(t) for t in tickets]
+        assert all(r[0] == 0 for r in res)
+        spans = {(r[2]["slot"], r[2]["t_dev_start"], r[2]["t_dev_end"]) for r in res}
+        assert all(0 <= a < b for _, a, b in spans)
+        overlaps = [(x, y) for x in spans for y in spans
+                    if x[0] != y[0] and x[1] < y[2] and y[1] < x[2]]
+        assert overlaps, f"no two slots' batches overlapped on the device: {sorted(spans, key=lambda s: s[1])}"
+        for i in range(0, 48, 5):
+            job = v3db.Job(trace=hosts[i].cuda(), log_blowup=3, cap_height=reqs[i][3])
+            ctx.commit(job)
+            torch.cuda.synchronize()
+            assert np.array_equal(res[i][1], v3db.to_host(job.cap)), f"request {i}"
