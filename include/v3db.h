@@ -141,6 +141,23 @@ v3db_status v3db_poseidon_permute(v3db_ctx *ctx, uint64_t *d_states, size_t coun
 v3db_status v3db_merkle_commit(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
                                uint32_t cap_height, uint64_t *d_tree, uint64_t *d_cap, v3db_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): v3db_merkle_commit with d_tree NULL,
+ * the tree levels held in a static device array of V3DB_NOALLOC_SCRATCH_BYTES instead of
+ * the context's pooled scratch. Nothing is allocated and nothing is freed by the call;
+ * the array exists on each device the library runs on until the process ends, and its
+ * device address is looked up once per device at v3db_ctx_create. It holds at most
+ * 2^20 leaves ((2^(log_leaves+1) - 2^cap_height) * 32 bytes <= 64 MiB). Every call on a
+ * device shares that device's array: calls that overlap on one device (on other streams
+ * or from other threads) race and must be ordered by the caller; the array keeps the
+ * last call's levels. No input validation pass runs (V3DB_VALIDATE is not honoured).
+ * d_mat [n_cols][2^log_leaves] device, column-major; d_cap [2^cap_height][4] device.
+ * Errors: INVALID_ARG (NULL ctx/d_mat/d_cap, n_cols == 0, cap_height > log_leaves),
+ * UNSUPPORTED (beyond the build limits or the static scratch), DEVICE. */
+#define V3DB_NOALLOC_SCRATCH_BYTES (64u << 20)
+v3db_status v3db_merkle_commit_noalloc(v3db_ctx *ctx, const uint64_t *d_mat, uint32_t n_cols, uint32_t log_leaves,
+                                       uint32_t cap_height, uint64_t *d_cap, v3db_stream stream);
+
 /* One commit job: LDE of the trace, leaf hashing, Merkle tree up to the cap. */
 typedef struct {
   const uint64_t *d_trace; /* [n_cols][2^log_rows], device */

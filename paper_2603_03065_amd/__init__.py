@@ -170,6 +170,7 @@ def lib():
         "v3db_lde": (i32, [vp, vp, u32, u32, u32, u64, i32, vp, vp]),
         "v3db_poseidon_permute": (i32, [vp, vp, sz, vp]),
         "v3db_merkle_commit": (i32, [vp, vp, u32, u32, u32, vp, vp, vp]),
+        "v3db_merkle_commit_noalloc": (i32, [vp, vp, u32, u32, u32, vp, vp]),
         "v3db_commit_batch": (i32, [vp, ctypes.POINTER(_Job), sz, vp]),
         "v3db_commit_batch_scratch_bytes": (sz, [ctypes.POINTER(_Job), sz]),
         "v3db_profile_enable": (i32, [vp, i32]),
@@ -342,6 +343,20 @@ class Context:
                                         _ptr(tree, tree_words, d, "tree"),
                                         _ptr(cap, (1 << cap_height) * 4 if cap_height < 63 else None, d, "cap"),
                                         _stream(stream)))
+        return cap
+
+    def merkle_commit_noalloc(self, mat, cap_height: int, cap, stream=None):
+        """merkle_commit whose tree levels live in the library's static device scratch
+        (v3db_merkle_commit_noalloc): allocates nothing; cap must be given."""
+        n_cols, nl = mat.shape
+        log_leaves = nl.bit_length() - 1
+        if 1 << log_leaves != nl:
+            raise ValueError("leaf count must be a power of two")
+        d = self.device
+        _check(lib().v3db_merkle_commit_noalloc(self._h, _ptr(mat, n_cols * nl, d, "mat"), n_cols, log_leaves,
+                                                cap_height,
+                                                _ptr(cap, (1 << cap_height) * 4 if cap_height < 63 else None, d,
+                                                     "cap"), _stream(stream)))
         return cap
 
     def open_batch(self, mat, tree, cap_height: int, idx, rows=None, paths=None, stream=None):

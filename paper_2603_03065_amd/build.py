@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libv3db.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["constants.cpp", "ntt.hip", "poseidon.hip", "batch.hip", "open.hip", "snapshot.hip", "multiset.hip", "fri.hip", "api.cpp", "server.cpp"]
+SOURCES = ["constants.cpp", "ntt.hip", "poseidon.hip", "batch.hip", "open.hip", "snapshot.hip", "multiset.hip", "fri.hip", "noalloc.hip", "api.cpp", "server.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

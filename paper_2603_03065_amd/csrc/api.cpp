@@ -246,6 +246,7 @@ v3db_status v3db_ctx_create(int device, uint64_t poseidon_seed, size_t hbm_budge
   if (st == V3DB_OK) st = build_twiddles(ctx);
   if (st == V3DB_OK) st = set_lde_kernel_attributes();
   if (st == V3DB_OK) st = set_batch_kernel_attributes();
+  if (st == V3DB_OK) st = noalloc_setup(device);
   if (st != V3DB_OK) {
     v3db_ctx_destroy(ctx);
     return st;

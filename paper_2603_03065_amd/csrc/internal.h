@@ -165,6 +165,10 @@ v3db_status enqueue_lde(v3db_ctx *ctx, const uint64_t *trace, uint32_t n_cols, u
                         uint32_t log_blowup, uint64_t shift, v3db_layout layout, uint64_t *lde,
                         uint64_t *scratch, hipStream_t stream);
 
+// The no-alloc entry point's static scratch: its address on `device` (noalloc.hip),
+// looked up once per device with that device current.
+v3db_status noalloc_setup(int device);
+
 // Phase timing: returns an event recorded on `stream` (or nullptr when not profiling).
 hipEvent_t prof_mark(v3db_ctx *ctx, hipStream_t stream);
 void prof_interval(v3db_ctx *ctx, int phase, hipEvent_t a, hipEvent_t b);
