@@ -132,9 +132,9 @@ def parse():
                     help="keep the default LDE schedules instead of tuning them before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (reference for the HBM byte counters)")
-    ap.add_argument("--cpu-sample-log-rows", type=int, default=15,
+    ap.add_argument("--cpu-sample-log-rows", type=int, default=17,
                     help="rows (log2) of the oracle's all-thread sample; same columns/layout/blowup/cap as the workload")
-    ap.add_argument("--cpu-sample-log-rows-1t", type=int, default=12,
+    ap.add_argument("--cpu-sample-log-rows-1t", type=int, default=13,
                     help="rows (log2) of the oracle's one-thread sample")
     ap.add_argument("--no-batch", action="store_true",
                     help="single-trace workloads: leave out the 64-trace batched vs per-trace comparison")

@@ -66,7 +66,7 @@ struct LdePlan {
 
 // Largest extension (log2 rows) whose pass-2 twiddles w_N^(k1 e) are kept as a
 // full table (8 N bytes per shape) instead of two lookups and a product.
-constexpr uint32_t ZTW_MAX_LOG = 22;
+constexpr uint32_t ZTW_MAX_LOG = 23;
 
 struct ScratchBuf {
   void *ptr = nullptr;
