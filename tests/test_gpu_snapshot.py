@@ -65,3 +65,14 @@ def test_snapshot_rejects_bad_shapes(v3db):
             ctx.snapshot_commit(1, 1, 3, 4, 2, z, z, z, z, z)
         with pytest.raises(v3db.V3dbError, match="limits"):
             ctx.snapshot_commit(14, 13, 1, 1, 1, z, z, z, z, z)
+
+
+def test_snapshot_gist1m_zkopt_full(v3db, poseidon, oracle_mod):
+    """512 lists x 4096 slots (N = 2^21 records), M = 8, D = 960, K = 256: centroid
+    sponges of 965 words and a codebook digest of 30 720 chained permutations."""
+    oracle_mod.set_threads(0)
+    shape = (9, 12, 8, 960, 256)
+    (mk, cb, roots), (omk, ocb, oroots, _) = _run(v3db, poseidon, shape, 7)
+    assert np.array_equal(roots, oroots)
+    assert np.array_equal(mk, omk)
+    assert np.array_equal(cb, ocb)
