@@ -34,15 +34,24 @@ __device__ __forceinline__ uint64_t sbox(uint64_t x) {
 
 // lo + hi * 2^32 for lo, hi < 2^46, to a relaxed value: with hi = hh*2^32 + hl,
 // the sum is lo + hh*2^64 + hl*2^32 = (hh*(2^32-1) + lo) + hl*2^32 (mod p); the
-// first part is one multiply-add below 2^47, the second adds hl to its high word
-// and a carry out of bit 64 is worth 2^32 - 1 again (the sum is then below
-// 2^47, far from overflowing once more).
+// first part t is one multiply-add below 2^47, the second adds hl to its high word,
+// and a carry c out of bit 64 is worth 2^32 - 1 again. The sum is then below 2^47, so
+// adding c*(2^32 - 1) cannot overflow; it is done on the two words with the carry
+// masks: low word t.lo - c (borrowing b only when t.lo = 0), high word + (c and not b).
 __device__ __forceinline__ uint64_t fold(uint64_t lo, uint64_t hi) {
   const uint64_t t = (uint64_t)(uint32_t)(hi >> 32) * gl::EPS + lo;
+#ifdef __HIP_DEVICE_COMPILE__
+  uint64_t c, b;
+  const uint32_t rh = gl::isa::add_co((uint32_t)(t >> 32), (uint32_t)hi, c);
+  const uint32_t r0 = gl::isa::subb0((uint32_t)t, c, b);
+  const uint32_t r1 = gl::isa::addc0(rh, c & ~b);
+  return ((uint64_t)r1 << 32) | r0;
+#else
   const uint32_t th = (uint32_t)(t >> 32);
   const uint32_t rh = th + (uint32_t)hi;
   const uint64_t r = ((uint64_t)rh << 32) | (uint32_t)t;
   return r + (rh < th ? gl::EPS : 0);
+#endif
 }
 
 // c + a * x, and acc += a * x, each as one v_mad_u64_u32 (the carry out is unused).

@@ -57,17 +57,13 @@ __device__ __forceinline__ MfLane mf_lane(const uint64_t *__restrict__ tab) {
   return L;
 }
 
-// permlane32 swap of 64-bit values: lanes < 32 keep a, lanes >= 32 get b from lane l - 32
-__device__ __forceinline__ uint64_t mf_up(uint64_t a, uint64_t b) {
+// v_permlane32_swap on 64-bit values: a of lanes 32..63 and b of lanes 0..31 trade
+// places (lane l + 32's a with lane l's b); a of lanes 0..31 and b of lanes 32..63 stay.
+__device__ __forceinline__ void mf_swap(uint64_t &a, uint64_t &b) {
   const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
   const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
-  return ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0];
-}
-// lanes < 32 get a from lane l + 32
-__device__ __forceinline__ uint64_t mf_down(uint64_t a) {
-  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)a, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(a >> 32), false, false);
-  return ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1];
+  a = ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0];
+  b = ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1];
 }
 
 // The permutation of the wave's 64 states (layout above). rc: the round-constant
@@ -88,11 +84,12 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
 #pragma unroll
         for (int jj = 0; jj < 6; jj++) S[u][jj] = sbox(S[u][jj]);
     } else {
-      const uint64_t y = sbox(mf_up(S[0][0], S[1][0]));
-      const uint64_t t = mf_down(y);
-      // selects, not a branch: a divergent branch here makes the compiler copy the state
-      S[0][0] = h == 0 ? y : S[0][0];
-      S[1][0] = h == 0 ? t : S[1][0];
+      // word 0 of permutation c + 32 (lane c's S[1][0]) trades places with the word lane
+      // c + 32 keeps in S[0][0] (word 6 of permutation c), so every lane's S[0][0] is a
+      // word 0; after the S-box the same exchange returns each value to where it was
+      mf_swap(S[0][0], S[1][0]);
+      S[0][0] = sbox(S[0][0]);
+      mf_swap(S[0][0], S[1][0]);
     }
     const uint64_t *kr = tab + MF_RCK + (size_t(r + 1) * WIDTH + 6 * h) * 2;
     uint32_t dw[2][6][2];
@@ -122,6 +119,9 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
         B[0] = (int)__builtin_amdgcn_perm(dw[u][1][half], dw[u][0][half], sel);
         B[1] = (int)__builtin_amdgcn_perm(dw[u][3][half], dw[u][2][half], sel);
         B[2] = (int)__builtin_amdgcn_perm(dw[u][5][half], dw[u][4][half], sel);
+        // (K slots 12..15 have zero entries in A, so this dword could hold anything; a
+        // register already holding a word, instead of a zero written before every
+        // product, measured 3 % slower)
         B[3] = 0;
         D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A, B, (mf_v16i){}, 0, 0, 0);
       }
