@@ -92,15 +92,15 @@ def hash_roofline(kernel: str, perms: int, seconds: float, path: str, workload: 
     return r
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when the
-    kernel's sources changed since the counters were taken or no run covers this workload."""
+def _traffic_record(kernel: str, workload: str):
+    """The committed rocprofv3 counter record of `kernel` on `workload` (profiles/traffic.json:
+    FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when there is none
+    or the kernel's sources changed since the counters were taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
-            rec = json.load(f)["kernels"][kernel]
-    except (OSError, KeyError, ValueError):
+            rec = json.load(f)["kernels"][kernel][workload]
+    except (OSError, KeyError, ValueError, TypeError):
         return None
     h = hashlib.sha256()
     try:
@@ -109,9 +109,24 @@ def measured_traffic(kernel: str, workload: str):
                 h.update(f.read())
     except (OSError, KeyError, TypeError):
         return None
-    if h.hexdigest()[:16] != rec["source_digest"] or rec["workload"] != workload:
-        return None
-    return rec["hbm_bytes_per_dispatch"]
+    return rec if h.hexdigest()[:16] == rec.get("source_digest") else None
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch of `kernel` from the committed counter runs, or None."""
+    rec = _traffic_record(kernel, workload)
+    return rec["hbm_bytes_per_dispatch"] if rec else None
+
+
+def measured_lde_traffic(workload: str):
+    """HBM bytes per step of the four LDE pass kernels from the committed counter runs, or None."""
+    total = 0.0
+    for k in ("k_lde_pass1", "k_lde_pass2i", "k_lde_pass2", "k_lde_pass3"):
+        rec = _traffic_record(k, workload)
+        if not rec or "dispatches_per_step" not in rec:
+            return None
+        total += rec["hbm_bytes_per_dispatch"] * rec["dispatches_per_step"]
+    return total
 
 
 def parse():
@@ -869,7 +884,7 @@ def main():
         "phases": {
             "lde": {"avg_ms": lde_avg_s * 1e3, "bound": "hbm", "achieved_GBps": lde_gbs, "peak_GBps": HBM_PEAK_GBS,
                     "frac": lde_gbs / HBM_PEAK_GBS, "algorithmic_bytes": elems * LDE_BYTES_PER_ELEMENT,
-                    "traffic": measured_traffic("lde_passes", args.workload)},
+                    "traffic": measured_lde_traffic(args.workload)},
             "leaf": {"avg_ms": leaf_avg_s * 1e3, "permutations": perms_leaf,
                      "permutations_per_s": perms_leaf / leaf_avg_s},
             "merkle": {"avg_ms": mk_avg_s * 1e3, "permutations": perms_merkle,

@@ -8,9 +8,18 @@ namespace {
 
 using namespace lde;
 
+// Tile of block x when tiles of 8 words per row leave each 128-byte line half used by
+// one tile and half by the next: blocks are dealt to the eight XCDs in turn, so tiles
+// 2i and 2i + 1 go to blocks 16q + r and 16q + 8 + r (same XCD r, dispatched 8 apart)
+// and the second reads the line from that XCD's L2. Identity for other grids.
+__device__ __forceinline__ int xcd_pair_tile(int x, int n, int logT) {
+  if (logT != 3 || (n & 15)) return x;
+  return (x & ~15) | ((x & 7) << 1) | ((x >> 3) & 1);
+}
+
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass1(LdeTask s, Twiddles tw) {
   extern __shared__ uint64_t sh[];
-  lde_pass1_tile(s, tw, sh, blockIdx.y, blockIdx.x);
+  lde_pass1_tile(s, tw, sh, blockIdx.y, xcd_pair_tile(blockIdx.x, gridDim.x, s.logT1));
 }
 
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass2i(LdeTask s, Twiddles tw) {
@@ -27,7 +36,7 @@ __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_e
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass3(LdeTask s, Twiddles tw, int col0) {
   extern __shared__ uint64_t sh[];
   const int col = col0 + blockIdx.y;
-  lde_pass3_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
+  lde_pass3_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, xcd_pair_tile(blockIdx.x, gridDim.x, s.logT3));
 }
 
 // log2 of the tile height: T * M <= 8192 words, T <= 2^cap, T <= the other dimension.
