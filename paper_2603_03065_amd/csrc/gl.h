@@ -73,6 +73,11 @@ __device__ __forceinline__ uint32_t subb(uint32_t a, uint32_t b, uint64_t bi, ui
   asm("v_subb_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(d), "=s"(bo) : "v"(a), "v"(b), "s"(bi));
   return d;
 }
+__device__ __forceinline__ uint32_t addc0_co(uint32_t a, uint64_t ci, uint64_t &co) {  // a + carry, carry out
+  uint32_t d;
+  asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(d), "=s"(co) : "v"(a), "s"(ci));
+  return d;
+}
 __device__ __forceinline__ uint32_t subb0(uint32_t a, uint64_t bi, uint64_t &bo) {  // a - borrow
   uint32_t d;
   asm("v_subb_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(d), "=s"(bo) : "v"(a), "s"(bi));
@@ -136,7 +141,19 @@ GL_HD uint64_t reduce128(uint64_t lo, uint64_t hi) {
 #endif
 }
 
-GL_HD uint64_t canon(uint64_t x) { return x >= P ? x - P : x; }
+GL_HD uint64_t canon(uint64_t x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  // x - p = x + (2^32 - 1) modulo 2^64 where x >= p, with the compare's mask as the
+  // borrow into the low word and the carry into the high word (which then wraps)
+  uint64_t bb;
+  const uint64_t m = __builtin_amdgcn_uicmpl(P - 1, x, 36 /* unsigned less than */);
+  const uint32_t r0 = isa::subb0((uint32_t)x, m, bb);
+  const uint32_t r1 = isa::addc0((uint32_t)(x >> 32), m & ~bb);
+  return ((uint64_t)r1 << 32) | r0;
+#else
+  return x >= P ? x - P : x;
+#endif
+}
 
 // x * 2^K (0 < K < 64), relaxed: the 128-bit product is a pair of shifts.
 template <int K>
@@ -199,19 +216,44 @@ GL_HD uint64_t mul(uint64_t a, uint64_t b) { return canon(mul_r(a, b)); }
 
 GL_HD uint64_t add(uint64_t a, uint64_t b) {  // a, b canonical
   // a + b < 2p: subtract p (add 2^64 - p = EPS modulo 2^64) when the sum carried
-  // out of 64 bits or is at least p; written without branches
+  // out of 64 bits or is at least p
+#ifdef __HIP_DEVICE_COMPILE__
+  // the sum on the carry chain; then + m * (2^32 - 1) for the mask m = carry | (s >= p)
+  // as a subtract-with-borrow on the low word and an add-with-carry on the high word
+  // (the high word wraps exactly when s >= p, giving s - p)
+  uint64_t c, c1, bb, m;
+  const uint32_t s0 = isa::add_co((uint32_t)a, (uint32_t)b, c1);
+  const uint32_t s1 = isa::addc((uint32_t)(a >> 32), (uint32_t)(b >> 32), c1, c);
+  const uint64_t sum = ((uint64_t)s1 << 32) | s0;
+  m = c | (uint64_t)__builtin_amdgcn_uicmpl(P - 1, sum, 36 /* unsigned less than */);
+  const uint32_t r0 = isa::subb0(s0, m, bb);
+  const uint32_t r1 = isa::addc0(s1, m & ~bb);
+  return ((uint64_t)r1 << 32) | r0;
+#else
   const uint64_t s = a + b, t = s + EPS;
   return ((s < a) | (s >= P)) ? t : s;
+#endif
 }
 
 GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical
   // a - b + p = d - 2^64 + p = d - EPS when the subtraction borrowed; the borrow
   // is taken from the carry chain rather than from a second comparison
+#ifdef __HIP_DEVICE_COMPILE__
+  // d - EPS = d + p (mod 2^64): low word + bw with carry k, high word + (2^32 - 1) * bw + k,
+  // i.e. minus (bw and not k)
+  uint64_t b1, bw, k, unused;
+  const uint32_t d0 = isa::sub_co((uint32_t)a, (uint32_t)b, b1);
+  const uint32_t d1 = isa::subb((uint32_t)(a >> 32), (uint32_t)(b >> 32), b1, bw);
+  const uint32_t r0 = isa::addc0_co(d0, bw, k);
+  const uint32_t r1 = isa::subb0(d1, bw & ~k, unused);
+  return ((uint64_t)r1 << 32) | r0;
+#else
   unsigned b1, bw;
   const uint32_t d0 = __builtin_subc((uint32_t)a, (uint32_t)b, 0u, &b1);
   const uint32_t d1 = __builtin_subc((uint32_t)(a >> 32), (uint32_t)(b >> 32), b1, &bw);
   const uint64_t d = ((uint64_t)d1 << 32) | d0;
   return d - (bw ? EPS : 0);
+#endif
 }
 
 // relaxed a + canonical b -> relaxed
