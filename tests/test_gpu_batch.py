@@ -90,13 +90,19 @@ def test_graph_replay_with_new_data(v3db, ctx, poseidon):
 
 
 def test_graph_cache_eviction(v3db, ctx, poseidon):
-    # more distinct shape lists than the cache holds; the first comes back at the end
-    lists = [[(3 + k % 5, 2 + k)] for k in range(11)] + [[(3, 2)]]
-    for k, shapes in enumerate(lists):
-        trs = [inputs.trace(50 + k, 0, nc, lr) for lr, nc in shapes]
+    """Ten distinct lists of two traces (a batch needs two natural-layout jobs), each
+    committed three times in an interleaved order: a list's first call runs without a
+    graph, its second captures one, its third replays it; with more lists than the 8
+    graphs kept, earlier graphs are evicted while later ones are in use, and the first
+    list comes back at the end. Every cap against the oracle."""
+    lists = [[(3 + k % 5, 2 + k), (4 + k % 3, 3)] for k in range(10)]
+    order = [k for r in range(3) for k in range(10)] + [0, 0]
+    for step, k in enumerate(order):
+        trs = [inputs.trace(50 + step, t, nc, lr) for t, (lr, nc) in enumerate(lists[k])]
         jobs = _jobs(v3db, trs, h=0)
         ctx.commit_batch(jobs)
-        assert np.array_equal(_host(v3db, jobs[0].cap), poseidon.commit(trs[0], 3, 7, 0, 0)[0])
+        for tr, j in zip(trs, jobs):
+            assert np.array_equal(_host(v3db, j.cap), poseidon.commit(tr, 3, 7, 0, 0)[0]), f"call {step}, list {k}"
 
 
 def test_small_group_cap_splits_batch(v3db, ctx):
