@@ -186,15 +186,44 @@ __device__ __forceinline__ void store_digests_mf(const uint64_t S[2][6], const M
   }
 }
 
-// Leaf digests of rows base .. base+63 of a column-major matrix with n_rows rows.
+// Leaf digests of rows base .. base+63 of a column-major matrix with n_rows rows: the
+// rate-8 overwrite sponge of sponge_mf with the loads written out. A lane with h = 0
+// absorbs columns q + 0..5 of each chunk, a lane with h = 1 columns q + 6, q + 7; word jj
+// of a chunk is at (column) * n_rows + row, a uniform offset from the lane's base pointer,
+// and whether the column exists is a uniform test (the branch on h is the only divergence).
 __device__ __forceinline__ void leaf_digests_mf(const uint64_t *__restrict__ mat, uint32_t n_cols, uint64_t n_rows,
                                                 uint64_t base, uint64_t *__restrict__ out, const MfLane &L,
                                                 const uint64_t *__restrict__ rc, const uint64_t *__restrict__ tab,
                                                 uint64_t *__restrict__ out2 = nullptr) {
   uint64_t S[2][6];
-  sponge_mf(
-      S, n_cols, [&](int u, uint64_t x) { return mat[x * n_rows + base + L.c + 32 * u]; },
-      [&](int u) { return base + L.c + 32 * u < n_rows; }, L, rc, tab);
+#pragma unroll
+  for (int u = 0; u < 2; u++)
+#pragma unroll
+    for (int jj = 0; jj < 6; jj++) S[u][jj] = 0;
+  const uint64_t row = base + L.c;
+  const bool live0 = row < n_rows, live1 = row + 32 < n_rows;
+  const uint64_t *p = mat + uint64_t(6 * L.h) * n_rows + row;  // column 6h of row base + c
+  for (uint32_t q = 0; q < n_cols; q += RATE) {
+    const uint64_t *pq = p + uint64_t(q) * n_rows;
+    if (L.h == 0) {
+#pragma unroll
+      for (int jj = 0; jj < 6; jj++)
+        if (q + jj < n_cols) {
+          const uint64_t *w = pq + uint64_t(jj) * n_rows;
+          S[0][jj] = live0 ? w[0] : 0;
+          S[1][jj] = live1 ? w[32] : 0;
+        }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 2; jj++)
+        if (q + 6 + jj < n_cols) {
+          const uint64_t *w = pq + uint64_t(jj) * n_rows;
+          S[0][jj] = live0 ? w[0] : 0;
+          S[1][jj] = live1 ? w[32] : 0;
+        }
+    }
+    permute_mf(S, L, rc, tab);
+  }
   store_digests_mf(S, L, base, n_rows, out, out2);
 }
 
