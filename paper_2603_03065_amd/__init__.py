@@ -6,8 +6,8 @@ and streams only: field elements live in int64 tensors used as raw 64-bit words
 (values >= 2^63 appear negative in torch and are the same bits), passed to the
 library as data pointers, with the current torch stream as the HIP stream.
 
-If libv3db.so has not been built this module raises on first use; there is no
-fallback path.
+If libv3db.so has not been built, or was built from other sources than the tree
+holds, this module raises on first use; there is no fallback path.
 """
 from __future__ import annotations
 
@@ -158,6 +158,17 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(python paper_2603_03065_amd/build.py)")
+    # a library built from other sources than the tree's would run other kernels than
+    # the ones read, tested and measured here: refuse it
+    from .build import source_digest
+    try:
+        with open(LIB_PATH + ".srcdigest") as f:
+            built = f.read().strip()
+    except OSError:
+        built = None
+    if built != source_digest():
+        raise ImportError(f"{LIB_PATH} was built from other sources than csrc/ and include/v3db.h "
+                          "hold now; rebuild it with __graft_entry__.build()")
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
     sig = {

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -27,6 +28,19 @@ COMMON = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 (16 hex digits) of every source the library is built from: csrc/ and the
+    public header, file names included, in sorted order."""
+    h = hashlib.sha256()
+    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h", ".cpp"))]
+    files.append(os.path.join(ROOT, "include", "v3db.h"))
+    for path in sorted(files):
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src + ".o")
     cmd = [HIPCC, "-x", "hip", "-c", *COMMON, "-o", obj, os.path.join(CSRC, src)]
@@ -42,8 +56,11 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    digest = source_digest()  # taken before linking: a source edited during the build fails the check
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    with open(LIB + ".srcdigest", "w") as f:
+        f.write(digest + "\n")
     if verbose:
         print("built", LIB)
     return LIB

@@ -119,3 +119,23 @@ def test_fri_commit_rejects_bad_arguments_without_device(v3db):
     lib = v3db.lib()
     assert lib.v3db_fri_commit(None, None, 4, 7, None, 1, 0, None, None, None, None) == 1
     assert b"NULL ctx" in lib.v3db_last_error()
+
+
+def test_library_is_built_from_the_tree_sources(v3db, tmp_path):
+    """The loader refuses a library whose recorded source digest differs from the tree's."""
+    from paper_2603_03065_amd.build import source_digest
+    with open(v3db.LIB_PATH + ".srcdigest") as f:
+        assert f.read().strip() == source_digest()
+    # a copy of the package whose digest file names other sources is refused
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2603_03065_amd"
+    shutil.copytree(os.path.dirname(v3db.LIB_PATH), pkg, ignore=shutil.ignore_patterns("_build", "__pycache__"))
+    (pkg / "libv3db.so.srcdigest").write_text("0" * 16 + "\n")
+    (tmp_path / "include").mkdir()
+    shutil.copy(HEADER, tmp_path / "include" / "v3db.h")
+    code = ("import paper_2603_03065_amd as m\n"
+            "try:\n    m.lib()\nexcept ImportError as e:\n    print('refused:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=300)
+    assert "refused:" in r.stdout and "rebuild" in r.stdout, r.stdout + r.stderr
