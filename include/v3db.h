@@ -86,6 +86,12 @@ void v3db_ctx_destroy(v3db_ctx *ctx);
  * string stays valid until the next call on this thread. */
 const char *v3db_last_error(void);
 
+/* Sixteen hex digits identifying the sources this library was built from (a SHA-256
+ * prefix over the HIP/C++ sources and this header, fixed at build time), so a loader can
+ * refuse a library built from other sources than it was given. Static string; no
+ * device work, no context needed. */
+const char *v3db_build_digest(void);
+
 /* Host copies of the derived Poseidon constants: rc [30][12], circ [12] (first
  * row of the circulant) and the number of 12-value draws the MDS search took.
  * Any output pointer may be NULL. */

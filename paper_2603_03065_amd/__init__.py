@@ -158,23 +158,23 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(python paper_2603_03065_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
     # a library built from other sources than the tree's would run other kernels than
     # the ones read, tested and measured here: refuse it
     from .build import source_digest
-    try:
-        with open(LIB_PATH + ".srcdigest") as f:
-            built = f.read().strip()
-    except OSError:
-        built = None
+    built = getattr(L, "v3db_build_digest", None)
+    if built is not None:
+        built.restype, built.argtypes = ctypes.c_char_p, []
+        built = built().decode()
     if built != source_digest():
         raise ImportError(f"{LIB_PATH} was built from other sources than csrc/ and include/v3db.h "
                           "hold now; rebuild it with __graft_entry__.build()")
-    L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
     sig = {
         "v3db_ctx_create": (i32, [i32, u64, sz, ctypes.POINTER(vp)]),
         "v3db_ctx_destroy": (None, [vp]),
         "v3db_last_error": (ctypes.c_char_p, []),
+        "v3db_build_digest": (ctypes.c_char_p, []),
         "v3db_poseidon_constants": (i32, [vp, vp, vp, ctypes.POINTER(u32)]),
         "v3db_ctx_hash_path": (i32, [vp]),
         "v3db_derive_poseidon_constants": (i32, [u64, vp, vp, ctypes.POINTER(u32)]),

@@ -42,7 +42,7 @@ def source_digest() -> str:
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, src + ".o")
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = [HIPCC, "-x", "hip", "-c", *COMMON, "-o", obj, os.path.join(CSRC, src)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -53,14 +53,15 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    # v3db_build_digest() returns the digest of the sources as they are when the build
+    # starts (a source edited during the build makes the loader refuse the result)
+    with open(os.path.join(OBJ, "build_digest.cpp"), "w") as f:
+        f.write('extern "C" const char *v3db_build_digest(void) { return "%s"; }\n' % source_digest())
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [os.path.join(OBJ, "build_digest.cpp")]))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
-    digest = source_digest()  # taken before linking: a source edited during the build fails the check
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
-    with open(LIB + ".srcdigest", "w") as f:
-        f.write(digest + "\n")
     if verbose:
         print("built", LIB)
     return LIB

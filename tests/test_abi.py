@@ -122,19 +122,18 @@ def test_fri_commit_rejects_bad_arguments_without_device(v3db):
 
 
 def test_library_is_built_from_the_tree_sources(v3db, tmp_path):
-    """The loader refuses a library whose recorded source digest differs from the tree's."""
+    """The library reports the digest of the sources it was built from, and the loader
+    refuses a library whose digest differs from the tree's."""
     from paper_2603_03065_amd.build import source_digest
-    with open(v3db.LIB_PATH + ".srcdigest") as f:
-        assert f.read().strip() == source_digest()
-    # a copy of the package whose digest file names other sources is refused
+    assert v3db.lib().v3db_build_digest().decode() == source_digest()
+    # a copy of the package whose header differs from the one the library was built with
     import shutil
     import subprocess
     import sys
     pkg = tmp_path / "paper_2603_03065_amd"
     shutil.copytree(os.path.dirname(v3db.LIB_PATH), pkg, ignore=shutil.ignore_patterns("_build", "__pycache__"))
-    (pkg / "libv3db.so.srcdigest").write_text("0" * 16 + "\n")
     (tmp_path / "include").mkdir()
-    shutil.copy(HEADER, tmp_path / "include" / "v3db.h")
+    (tmp_path / "include" / "v3db.h").write_text(open(HEADER).read() + "\n/* edited */\n")
     code = ("import paper_2603_03065_amd as m\n"
             "try:\n    m.lib()\nexcept ImportError as e:\n    print('refused:', e)\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=300)
