@@ -93,8 +93,9 @@ __global__ void __launch_bounds__(POS_THREADS) k_batch_leaf(const BJob *__restri
   }
 }
 
-// The same with the matrix-core linear layer: each wave covers 64 consecutive rows.
-__global__ void __launch_bounds__(POS_THREADS) k_batch_leaf_mf(const BJob *__restrict__ jobs,
+// The same with the matrix-core linear layer: each wave covers 64 consecutive rows
+// (held to 128 VGPRs, four waves per SIMD, as the single-trace leaf kernel).
+__global__ void __launch_bounds__(POS_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_batch_leaf_mf(const BJob *__restrict__ jobs,
                                                                 const BRange *__restrict__ ranges, int n_ranges,
                                                                 const uint64_t *__restrict__ rc,
                                                                 const uint64_t *__restrict__ tab) {

@@ -11,17 +11,23 @@
 // The linear layer y_i = sum_j a[(j-i) mod 12] s_j is exact over the integers
 // before the reduction, and it is computed limb by limb: with b_jk byte k of s_j,
 //   y_i = sum_k 2^(8k) sum_j C_ij b_jk.
-// v_mfma_i32_32x32x32_i8 (signed bytes, int32 sums) forms sum_j C_ij b_jk for one
-// limb k of the 32 permutations of one half of the wave:
+// v_mfma_i32_32x32x32_i8 (signed bytes, int32 sums) forms sum_j C_ij b_jk for two
+// limbs k = 2p, 2p + 1 of the 32 permutations of one half of the wave:
 //   * B column = one permutation; a lane supplies the K slots of its half
-//     (16h .. 16h+15), slot 2jj + part holding b'_jk = b_jk - 128 of its word jj
-//     (the byte XOR 0x80 read as signed) for both parts;
-//   * A row for output i holds ceil(C/2) in part 0 and floor(C/2) in part 1 of
-//     word j, so the two parts add to C (every entry must be at most 254 so the
-//     halves fit int8; the host checks and otherwise keeps the VALU form);
+//     (16h .. 16h+15), slot 4q + 2w + l holding b'_jk, k = 2p + l, of its word
+//     jj = 2q + w, with b' = b - 128 (the byte XOR 0x80 read as signed); slots 12..15
+//     are unused (zero in A);
+//   * a circulant entry C may reach 254, beyond int8, so it is split between two
+//     matrices, A1 holding ceil(C/2) and A2 floor(C/2), and the matrix core adds the two
+//     products (the second takes the first's result as its addend); every entry must
+//     be at most 254 (the host checks and otherwise keeps the VALU form);
+//   * the A row of output i and limb l holds the half entries of words j in the slots
+//     of limb l, zero in those of the other limb;
 //   * D row 8(e/4) + 4h + e%4 of column c lands in lane 32h + c, element e: the
-//     host puts output i = 6h + ii in row 8(ii/4) + 4h + ii%4, so each lane
-//     receives exactly the outputs for the words it holds (e = ii).
+//     host puts output i = 6h + ii, limb l in the row of element e = 6l + ii, so each
+//     lane receives exactly the outputs for the words it holds, both limbs.
+// One v_perm then packs two limbs of two words, and a round takes 24 of them for
+// eight limbs of twelve words (one limb per product took 48).
 // With b' = b - 128, sum_k 2^(8k) D_ik = y_i - 128 R G, R = sum_j C_ij (the same
 // for every row of a circulant) and G = sum_k 2^(8k). Each output accumulates
 // lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ...,
@@ -38,7 +44,7 @@ typedef int mf_v4i __attribute__((ext_vector_type(4)));
 typedef int mf_v16i __attribute__((ext_vector_type(16)));
 
 struct MfLane {
-  mf_v4i A;     // this lane's 16 bytes of the matrix
+  mf_v4i A1, A2;  // this lane's 16 bytes of each half matrix
   int mult[4];  // 1, 2^8, 2^16, 2^24 read from the table: each term stays one v_mad_i64_i32
   int h, c;
 };
@@ -50,7 +56,10 @@ __device__ __forceinline__ MfLane mf_lane(const uint64_t *__restrict__ tab) {
   L.c = l & 31;
   const uint32_t *am = reinterpret_cast<const uint32_t *>(tab + MF_AMAT) + l * 4;
 #pragma unroll
-  for (int q = 0; q < 4; q++) L.A[q] = (int)am[q];
+  for (int q = 0; q < 4; q++) {
+    L.A1[q] = (int)am[q];
+    L.A2[q] = (int)am[64 * 4 + q];
+  }
   const int *m = reinterpret_cast<const int *>(tab + MF_MULT);
 #pragma unroll
   for (int q = 0; q < 4; q++) L.mult[q] = m[q];
@@ -107,34 +116,38 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
       hi[0][ii] = hi[1][ii] = (int64_t)kr[2 * ii + 1];
     }
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-      const uint32_t kk = k & 3, half = k >> 2;
-      // bytes kk of two words, each twice (parts 0 and 1): v_perm selectors 0-3 pick
+    for (int p = 0; p < 4; p++) {
+      const uint32_t kk = (2 * p) & 3, half = p >> 1;
+      // bytes kk and kk + 1 (limbs 2p, 2p + 1) of two words: v_perm selectors 0-3 pick
       // from the second source, 4-7 from the first
-      const uint32_t sel = kk | (kk << 8) | ((kk + 4) << 16) | ((kk + 4) << 24);
-      mf_v16i D[2];
+      const uint32_t sel = kk | ((kk + 1) << 8) | ((kk + 4) << 16) | ((kk + 5) << 24);
+      mf_v4i B[2];
 #pragma unroll
       for (int u = 0; u < 2; u++) {
-        mf_v4i B;
-        B[0] = (int)__builtin_amdgcn_perm(dw[u][1][half], dw[u][0][half], sel);
-        B[1] = (int)__builtin_amdgcn_perm(dw[u][3][half], dw[u][2][half], sel);
-        B[2] = (int)__builtin_amdgcn_perm(dw[u][5][half], dw[u][4][half], sel);
-        // (K slots 12..15 have zero entries in A, so this dword could hold anything; a
-        // register already holding a word, instead of a zero written before every
-        // product, measured 3 % slower)
-        B[3] = 0;
-        D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A, B, (mf_v16i){}, 0, 0, 0);
+        B[u][0] = (int)__builtin_amdgcn_perm(dw[u][1][half], dw[u][0][half], sel);
+        B[u][1] = (int)__builtin_amdgcn_perm(dw[u][3][half], dw[u][2][half], sel);
+        B[u][2] = (int)__builtin_amdgcn_perm(dw[u][5][half], dw[u][4][half], sel);
+        B[u][3] = 0;  // K slots 12..15: zero entries in A
       }
-      // both products issued before either is read: the second runs on the matrix
-      // core while the first one's results are recombined
+      mf_v16i D[2];
+#pragma unroll
+      for (int u = 0; u < 2; u++) D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A1, B[u], (mf_v16i){}, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 2; u++) D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A2, B[u], D[u], 0, 0, 0);
+      // all four products issued before any is read: the matrix core runs the later
+      // ones while the earlier results are recombined
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int ii = 0; ii < 6; ii++) {
-          if (k < 4) lo[u][ii] += (int64_t)D[u][ii] * (int64_t)L.mult[kk];
-          else hi[u][ii] += (int64_t)D[u][ii] * (int64_t)L.mult[kk];
-        }
+        for (int l = 0; l < 2; l++)
+#pragma unroll
+          for (int ii = 0; ii < 6; ii++) {
+            const int k = 2 * p + l;
+            const int64_t t = (int64_t)D[u][6 * l + ii] * (int64_t)L.mult[k & 3];
+            if (k < 4) lo[u][ii] += t;
+            else hi[u][ii] += t;
+          }
     }
 #pragma unroll
     for (int u = 0; u < 2; u++)
