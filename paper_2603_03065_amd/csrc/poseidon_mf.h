@@ -30,7 +30,10 @@
 // eight limbs of twelve words (one limb per product took 48).
 // With b' = b - 128, sum_k 2^(8k) D_ik = y_i - 128 R G, R = sum_j C_ij (the same
 // for every row of a circulant) and G = sum_k 2^(8k). Each output accumulates
-// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ...,
+// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ..., a limb
+// pair's two sums first joined in 32 bits, then one 64-bit multiply-add per pair
+// (as many instructions as one multiply-add per limb, but half the 64-bit products,
+// which measured faster: the hash kernels run at the card's power limit),
 // K = 128 R (2^24 + 2^16 + 2^8 + 1) making both non-negative (D_ik >= -128 R) and
 // below 2^46, then fold(lo, hi) gives the relaxed output exactly as in the VALU
 // form. The start values K + next round's constant come from a small table.
@@ -137,17 +140,17 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
       // all four products issued before any is read: the matrix core runs the later
       // ones while the earlier results are recombined
       __builtin_amdgcn_sched_barrier(0);
+      // the two limbs first added in 32 bits (|D| < 2^19, so D_2p + 2^8 D_2p+1 fits),
+      // then one 64-bit multiply-add per word and limb pair
 #pragma unroll
       for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int l = 0; l < 2; l++)
-#pragma unroll
-          for (int ii = 0; ii < 6; ii++) {
-            const int k = 2 * p + l;
-            const int64_t t = (int64_t)D[u][6 * l + ii] * (int64_t)L.mult[k & 3];
-            if (k < 4) lo[u][ii] += t;
-            else hi[u][ii] += t;
-          }
+        for (int ii = 0; ii < 6; ii++) {
+          const int32_t pr = (int32_t)(((uint32_t)D[u][6 + ii] << 8) + (uint32_t)D[u][ii]);
+          const int64_t t = (int64_t)pr * (int64_t)L.mult[(2 * p) & 3];
+          if (p < 2) lo[u][ii] += t;
+          else hi[u][ii] += t;
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; u++)
