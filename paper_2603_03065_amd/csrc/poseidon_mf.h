@@ -30,13 +30,13 @@
 // eight limbs of twelve words (one limb per product took 48).
 // With b' = b - 128, sum_k 2^(8k) D_ik = y_i - 128 R G, R = sum_j C_ij (the same
 // for every row of a circulant) and G = sum_k 2^(8k). Each output accumulates
-// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ..., a limb
-// pair's two sums first joined in 32 bits, then one 64-bit multiply-add per pair
-// (as many instructions as one multiply-add per limb, but half the 64-bit products,
-// which measured faster: the hash kernels run at the card's power limit),
+// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ...,
 // K = 128 R (2^24 + 2^16 + 2^8 + 1) making both non-negative (D_ik >= -128 R) and
 // below 2^46, then fold(lo, hi) gives the relaxed output exactly as in the VALU
-// form. The start values K + next round's constant come from a small table.
+// form. The start values K + next round's constant come from a small table. A limb
+// pair's two sums are first joined in 32 bits (|D| < 2^19), then added with one 64-bit
+// multiply-add: as many instructions as one multiply-add per limb, but half the 64-bit
+// products, which measured faster (the hash kernels run at the card's power limit).
 #pragma once
 #include "poseidon_dev.h"
 
