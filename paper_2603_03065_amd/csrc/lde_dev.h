@@ -32,6 +32,8 @@
 #pragma once
 #include "internal.h"
 
+#include <type_traits>
+
 namespace v3db {
 namespace lde {
 
@@ -182,9 +184,11 @@ __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, 
 // Whole transforms over the rows: radix-8 passes, then one radix-4 or radix-2
 // pass for the remaining bits. Each pass ends with a barrier.
 // Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
-// were done another way).
+// were done another way). With leave_r2, a final radix-2 pass is not run but left
+// to the caller's reader (r2_pair), and the return value says whether it was.
 template <bool INV>
-__device__ __forceinline__ void dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs, const uint64_t *__restrict__ bfly) {
+__device__ __forceinline__ bool dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs,
+                                              const uint64_t *__restrict__ bfly, bool leave_r2 = false) {
   int logS = logS0;
   for (; logS >= 3; logS -= 3) {
     if (logS > 3) dif_pass<8, INV, true>(sh, T, logM, rs, logS, bfly);
@@ -195,14 +199,28 @@ __device__ __forceinline__ void dif_rows_from(uint64_t *sh, int T, int logM, int
     dif_pass<4, INV, false>(sh, T, logM, rs, 2, bfly);
     __syncthreads();
   } else if (logS == 1) {
+    if (leave_r2) return true;
     dif_pass<2, INV, false>(sh, T, logM, rs, 1, bfly);
     __syncthreads();
   }
+  return false;
 }
 
 template <bool INV>
-__device__ __forceinline__ void dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ bfly) {
-  dif_rows_from<INV>(sh, T, logM, logM, rs, bfly);
+__device__ __forceinline__ bool dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ bfly,
+                                         bool leave_r2 = false) {
+  return dif_rows_from<INV>(sh, T, logM, logM, rs, bfly, leave_r2);
+}
+
+// The last radix-2 pass of a row transform (left by dif_rows_from) done by its reader:
+// for a frequency f < M/2 (M = 2^logM) the butterfly's inputs are at positions brev(f)
+// (even) and brev(f) + 1 of the row, and its outputs are frequencies f (x0) and
+// f + M/2 (x1). The pass has no twiddles in either direction.
+__device__ __forceinline__ void r2_pair(const uint64_t *row, int f, int logM, uint64_t &x0, uint64_t &x1) {
+  const int w = swz(brev(f, logM));  // swz(w + 1) = swz(w) ^ 1 for even w
+  const uint64_t a = row[w], b = row[w ^ 1];
+  x0 = gl::add(a, b);
+  x1 = gl::sub(a, b);
 }
 
 // One trace's LDE as the passes see it. Column c of the trace is trace + c*n,
@@ -242,24 +260,52 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
       total, [&](int e) { return a[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))]; },
       [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT1)] = v; });
   __syncthreads();
-  dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv);
+  const bool r2 = dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv, true);
   const int shl = TW_LOG - s.L;
   constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
+  // w_n^(-j2 k1) = hi[x >> TW_HALF] * lo[x & lo_mask] with x = (j2 k1 mod n) << shl.
+  // Every lane requests the table words of all its elements before the first product
+  // (lanes past the end read the last element instead and store nothing), and every
+  // product is formed unconditionally, so no load is left outstanding on any path.
+  auto twiddled = [&](int t, int k1, uint64_t v) {
+    const uint32_t ex = (uint32_t)((uint64_t(j2_0 + t) * k1) & (n - 1));
+    const uint32_t x = ex << shl;
+    const uint64_t w = gl::mul(tw.inv_hi[x >> TW_HALF], tw.inv_lo[x & lo_mask]);
+    return ex ? gl::mul(v, w) : v;
+  };
+  if (r2) {
+    // the transforms' last radix-2 pass fused here: pair e gives k1 and k1 + n1/2
+    const int pairs = total >> 1;
+    for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
+      uint64_t r[OUT_BATCH];
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH / 2; u++) {
+        const int e = min(e0 + u * LDE_THREADS, pairs - 1);
+        const int t = e & (T - 1), k1 = e >> s.logT1;
+        uint64_t x0, x1;
+        r2_pair(sh + t * rs, k1, s.L1, x0, x1);
+        r[2 * u] = twiddled(t, k1, x0);
+        r[2 * u + 1] = twiddled(t, k1 + (n1 >> 1), x1);
+      }
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH / 2; u++) {
+        const int e = e0 + u * LDE_THREADS;
+        if (e < pairs) {
+          const int t = e & (T - 1), k1 = e >> s.logT1;
+          y[size_t(k1) * n2 + j2_0 + t] = r[2 * u];
+          y[size_t(k1 + (n1 >> 1)) * n2 + j2_0 + t] = r[2 * u + 1];
+        }
+      }
+    }
+    return;
+  }
   for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
-    // w_n^(-j2 k1) = hi[x >> TW_HALF] * lo[x & lo_mask] with x = (j2 k1 mod n) << shl.
-    // Every lane requests the table words of all its elements before the first product
-    // (lanes past the end read the last element instead and store nothing), and every
-    // product is formed unconditionally, so no load is left outstanding on any path.
     uint64_t r[OUT_BATCH];
 #pragma unroll
     for (int u = 0; u < OUT_BATCH; u++) {
       const int e = min(e0 + u * LDE_THREADS, total - 1);
       const int t = e & (T - 1), k1 = e >> s.logT1;
-      const uint32_t ex = (uint32_t)((uint64_t(j2_0 + t) * k1) & (n - 1));
-      const uint32_t x = ex << shl;
-      const uint64_t v = sh[t * rs + swz(brev(k1, s.L1))];
-      const uint64_t w = gl::mul(tw.inv_hi[x >> TW_HALF], tw.inv_lo[x & lo_mask]);
-      r[u] = ex ? gl::mul(v, w) : v;
+      r[u] = twiddled(t, k1, sh[t * rs + swz(brev(k1, s.L1))]);
     }
 #pragma unroll
     for (int u = 0; u < OUT_BATCH; u++) {
@@ -315,7 +361,33 @@ __device__ __forceinline__ void lde_pass2i_tile(const LdeTask &s, const Twiddles
       total, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
       [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
   __syncthreads();
-  dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
+  if (dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv, true)) {
+    // the transforms' last radix-2 pass fused here: pair e gives i and i + n2/2
+    const int pairs = total >> 1, lh = s.L2 - 1;
+    for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
+      uint64_t r[OUT_BATCH];
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH / 2; u++) {
+        const int e = min(e0 + u * LDE_THREADS, pairs - 1);
+        const int t = e >> lh, i = e & ((1 << lh) - 1);
+        uint64_t x0, x1;
+        r2_pair(sh + t * rs, i, s.L2, x0, x1);
+        const uint64_t sc = s.scale[k1_0 + t];
+        r[2 * u] = gl::mul(x0, sc);
+        r[2 * u + 1] = gl::mul(x1, sc);
+      }
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH / 2; u++) {
+        const int e = e0 + u * LDE_THREADS;
+        if (e < pairs) {
+          uint64_t *row = y + size_t(k1_0 + (e >> lh)) * n2 + (e & ((1 << lh) - 1));
+          row[0] = r[2 * u];
+          row[n2 >> 1] = r[2 * u + 1];
+        }
+      }
+    }
+    return;
+  }
   for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
     uint64_t r[OUT_BATCH];
 #pragma unroll
@@ -386,40 +458,58 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
     default: twist_stage<16>(s, sh, rs, n_in, total_in, c); break;
   }
   __syncthreads();
-  dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd);
+  const bool r2 = dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd, true);
   const int total_out = T << LW;
   const int shl = TW_LOG - logN;
   constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
   // w_N^(k1 e) for each element (one ztw word, or two words of the two-level table),
   // requested for a batch of elements before the first product; lanes past the end read
   // the last element and store nothing, and every product is formed unconditionally
-  if (s.ztw) {
-    for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
-      uint64_t r[OUT_BATCH];
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH; u++) {
-        const int e = min(e0 + u * LDE_THREADS, total_out - 1);
-        const int t = e >> LW, f = e & (W - 1);
-        r[u] = gl::mul(sh[t * rs + swz(brev(f, LW))], s.ztw[(size_t(k1_0 + t) << LW) + f]);
-      }
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH; u++) {
-        const int e = e0 + u * LDE_THREADS;
-        if (e < total_out) zc[(size_t(k1_0 + (e >> LW)) << LW) + (e & (W - 1))] = r[u];
-      }
-    }
-  } else {
-    for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
-      uint64_t r[OUT_BATCH];
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH; u++) {
-        const int e = min(e0 + u * LDE_THREADS, total_out - 1);
-        const int t = e >> LW, f = e & (W - 1);
+  auto out_loops = [&](auto use_ztw) {
+    constexpr bool Z = decltype(use_ztw)::value;
+    auto twiddled = [&](int t, int f, uint64_t v) {
+      if constexpr (Z) {
+        return gl::mul(v, s.ztw[(size_t(k1_0 + t) << LW) + f]);
+      } else {
         const uint32_t ex = (uint32_t)((uint64_t(k1_0 + t) * f) & (N - 1));
         const uint32_t x = ex << shl;
-        const uint64_t v = sh[t * rs + swz(brev(f, LW))];
         const uint64_t w = gl::mul(tw.fwd_hi[x >> TW_HALF], tw.fwd_lo[x & lo_mask]);
-        r[u] = ex ? gl::mul(v, w) : v;
+        return ex ? gl::mul(v, w) : v;
+      }
+    };
+    if (r2) {
+      // the transforms' last radix-2 pass fused here: pair e gives f and f + W/2
+      const int pairs = total_out >> 1, lh = LW - 1;
+      for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
+        uint64_t r[OUT_BATCH];
+#pragma unroll
+        for (int u = 0; u < OUT_BATCH / 2; u++) {
+          const int e = min(e0 + u * LDE_THREADS, pairs - 1);
+          const int t = e >> lh, f = e & ((1 << lh) - 1);
+          uint64_t x0, x1;
+          r2_pair(sh + t * rs, f, LW, x0, x1);
+          r[2 * u] = twiddled(t, f, x0);
+          r[2 * u + 1] = twiddled(t, f + (W >> 1), x1);
+        }
+#pragma unroll
+        for (int u = 0; u < OUT_BATCH / 2; u++) {
+          const int e = e0 + u * LDE_THREADS;
+          if (e < pairs) {
+            uint64_t *row = zc + (size_t(k1_0 + (e >> lh)) << LW) + (e & ((1 << lh) - 1));
+            row[0] = r[2 * u];
+            row[W >> 1] = r[2 * u + 1];
+          }
+        }
+      }
+      return;
+    }
+    for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
+      uint64_t r[OUT_BATCH];
+#pragma unroll
+      for (int u = 0; u < OUT_BATCH; u++) {
+        const int e = min(e0 + u * LDE_THREADS, total_out - 1);
+        const int t = e >> LW, f = e & (W - 1);
+        r[u] = twiddled(t, f, sh[t * rs + swz(brev(f, LW))]);
       }
 #pragma unroll
       for (int u = 0; u < OUT_BATCH; u++) {
@@ -427,7 +517,9 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
         if (e < total_out) zc[(size_t(k1_0 + (e >> LW)) << LW) + (e & (W - 1))] = r[u];
       }
     }
-  }
+  };
+  if (s.ztw) out_loops(std::true_type{});
+  else out_loops(std::false_type{});
 }
 
 // Pass 3, tile = T consecutive columns e of Z (of column col). In natural
@@ -515,11 +607,25 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
       total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
       [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT3)] = v; });
   __syncthreads();
-  dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd);
+  // bit-reversed layout: the last radix-2 pass is left to the writer, which stores each
+  // butterfly's two outputs (positions 2q and 2q + 1, adjacent in the output row) together
+  const bool r2 = dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd, s.bitrev != 0);
   if (!s.bitrev) {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e & (T - 1), m2 = e >> s.logT3;
       out[size_t(e0 + t) + size_t(W) * m2] = sh[t * rs + swz(brev(m2, s.L1))];
+    }
+  } else if (r2) {
+    const int lh = s.L1 - 1;
+    for (int e = threadIdx.x; e < (total >> 1); e += blockDim.x) {
+      const int t = e >> lh, q = e & ((1 << lh) - 1);
+      const uint64_t *row = sh + t * rs;
+      const int w = swz(2 * q);  // swz(2q + 1) = swz(2q) ^ 1
+      const uint64_t a = row[w], b = row[w ^ 1];
+      ulonglong2 v;
+      v.x = gl::add(a, b);
+      v.y = gl::sub(a, b);
+      *reinterpret_cast<ulonglong2 *>(out + size_t(brev(e0 + t, LW)) * n1 + 2 * q) = v;
     }
   } else {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
