@@ -248,6 +248,36 @@ __device__ __forceinline__ int lde_tiles2(const LdeTask &t) { return (1 << t.L1)
 __device__ __forceinline__ int lde_tiles2i(const LdeTask &t) { return (1 << t.L1) >> t.logT2i; }
 __device__ __forceinline__ int lde_tiles3(const LdeTask &t) { return (1 << (t.L2 + t.b)) >> t.logT3; }
 
+// The first radix-8 pass of a row transform (sub-blocks of the whole row, 2^logM words)
+// with its inputs read straight from global memory: word w of row t is src(t, w). The
+// butterflies are numbered with t fastest, so with T >= 16 rows the lanes of a
+// half-wave read 16 consecutive words (the rows are adjacent columns of a matrix).
+template <bool INV, class Src>
+__device__ __forceinline__ void first_pass_global(uint64_t *sh, int T, int logT, int logM, int rs,
+                                                  const uint64_t *__restrict__ bfly, Src src) {
+  const int logStride = logM - 3, stride = 1 << logStride;
+  const int nb = T << logStride;
+  const uint64_t *rows = bfly + 8 * bfly_row0(logM);
+  for (int b = threadIdx.x; b < nb; b += LDE_THREADS) {
+    const int t = b & (T - 1), i = b >> logT;
+    uint64_t v[8], w[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = src(t, i + (j << logStride));
+    const ulonglong2 *trow = reinterpret_cast<const ulonglong2 *>(rows + 8 * i);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const ulonglong2 x = trow[k];
+      w[2 * k] = x.x, w[2 * k + 1] = x.y;
+    }
+    reg_dif<8, INV>(v);
+    uint64_t *row = sh + t * rs;
+    const int wb = swz(i);
+    row[wb] = v[0];
+#pragma unroll
+    for (int j = 1; j < 8; j++) row[wb ^ swz(j << logStride)] = gl::mul(v[j], w[j]);
+  }
+}
+
 // Pass 1, tile = T consecutive j2 of column col.
 __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int tile) {
   const int n1 = 1 << s.L1, n2 = 1 << s.L2, T = 1 << s.logT1, rs = n1 + 1;
@@ -256,11 +286,20 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
   uint64_t *y = s.y + size_t(col) * n;
   const int j2_0 = tile << s.logT1;
   const int total = T * n1;
-  stage_tile(
-      total, [&](int e) { return a[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))]; },
-      [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT1)] = v; });
-  __syncthreads();
-  const bool r2 = dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv, true);
+  bool r2;
+  if (s.L1 >= 4) {
+    // the first radix-8 pass reads the trace straight from global memory
+    first_pass_global<true>(sh, T, s.logT1, s.L1, rs, tw.bfly_inv,
+                            [&](int t, int w) { return a[size_t(w) * n2 + j2_0 + t]; });
+    __syncthreads();
+    r2 = dif_rows_from<true>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_inv, true);
+  } else {
+    stage_tile(
+        total, [&](int e) { return a[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))]; },
+        [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT1)] = v; });
+    __syncthreads();
+    r2 = dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv, true);
+  }
   const int shl = TW_LOG - s.L;
   constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
   // w_n^(-j2 k1) = hi[x >> TW_HALF] * lo[x & lo_mask] with x = (j2 k1 mod n) << shl.
@@ -525,36 +564,6 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
 // Pass 3, tile = T consecutive columns e of Z (of column col). In natural
 // layout the words it reads, Z[k1][e] at k1*W + e, are exactly the words it
 // writes, LDE[e + W*m2], so it can run in place.
-// The first radix-8 pass of a row transform (sub-blocks of the whole row, 2^logM words)
-// with its inputs read straight from global memory: word w of row t is src(t, w). The
-// butterflies are numbered with t fastest, so with T >= 16 rows the lanes of a
-// half-wave read 16 consecutive words (the rows are adjacent columns of a matrix).
-template <bool INV, class Src>
-__device__ __forceinline__ void first_pass_global(uint64_t *sh, int T, int logT, int logM, int rs,
-                                                  const uint64_t *__restrict__ bfly, Src src) {
-  const int logStride = logM - 3, stride = 1 << logStride;
-  const int nb = T << logStride;
-  const uint64_t *rows = bfly + 8 * bfly_row0(logM);
-  for (int b = threadIdx.x; b < nb; b += LDE_THREADS) {
-    const int t = b & (T - 1), i = b >> logT;
-    uint64_t v[8], w[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) v[j] = src(t, i + (j << logStride));
-    const ulonglong2 *trow = reinterpret_cast<const ulonglong2 *>(rows + 8 * i);
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const ulonglong2 x = trow[k];
-      w[2 * k] = x.x, w[2 * k + 1] = x.y;
-    }
-    reg_dif<8, INV>(v);
-    uint64_t *row = sh + t * rs;
-    const int wb = swz(i);
-    row[wb] = v[0];
-#pragma unroll
-    for (int j = 1; j < 8; j++) row[wb ^ swz(j << logStride)] = gl::mul(v[j], w[j]);
-  }
-}
-
 // The last pass of a row transform (radix R on sub-blocks of R consecutive words, no
 // twiddles) with its outputs written straight to global memory: position w of row t
 // (frequency bitrev(w)) goes to dst(t, w, value). Butterflies numbered with t fastest.
@@ -603,13 +612,22 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
     else last_pass_global<2, false>(sh, T, s.logT3, s.L1, rs, dst);
     return;
   }
-  stage_tile(
-      total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
-      [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT3)] = v; });
-  __syncthreads();
-  // bit-reversed layout: the last radix-2 pass is left to the writer, which stores each
-  // butterfly's two outputs (positions 2q and 2q + 1, adjacent in the output row) together
-  const bool r2 = dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd, s.bitrev != 0);
+  bool r2;
+  if (s.bitrev && s.L1 >= 4) {
+    // the first radix-8 pass reads Z straight from global memory, as in natural layout
+    first_pass_global<false>(sh, T, s.logT3, s.L1, rs, tw.bfly_fwd,
+                             [&](int t, int w) { return zc[(size_t(w) << LW) + e0 + t]; });
+    __syncthreads();
+    r2 = dif_rows_from<false>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_fwd, true);
+  } else {
+    stage_tile(
+        total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
+        [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT3)] = v; });
+    __syncthreads();
+    // bit-reversed layout: the last radix-2 pass is left to the writer, which stores each
+    // butterfly's two outputs (positions 2q and 2q + 1, adjacent in the output row) together
+    r2 = dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd, s.bitrev != 0);
+  }
   if (!s.bitrev) {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e & (T - 1), m2 = e >> s.logT3;
