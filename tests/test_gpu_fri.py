@@ -97,10 +97,13 @@ def test_fri_calls_of_different_sizes_on_one_context(v3db, poseidon, oracle_mod)
             d = v3db.to_device(f0)
             if stream is not None:
                 stream.wait_stream(torch.cuda.current_stream())
+                # the codeword is read on the side stream: its block must not be handed
+                # to the next call's upload (on the default stream) before that work ends
+                d.record_stream(stream)
             folded, caps, trees = ctx.fri_commit(d, 7, betas, h, want_trees=True, stream=stream)
-            outs.append((f0, betas, h, folded, caps, trees))
+            outs.append((f0, betas, h, folded, caps, trees, d))
         torch.cuda.synchronize()
-        for f0, betas, h, folded, caps, trees in outs:
+        for f0, betas, h, folded, caps, trees, _ in outs:
             ofolded, ocaps, otrees = poseidon.fri_commit(f0, 7, betas, h, want_trees=True)
             assert np.array_equal(v3db.to_host(folded), ofolded)
             assert np.array_equal(v3db.to_host(caps), ocaps)
