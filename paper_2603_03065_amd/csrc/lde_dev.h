@@ -184,43 +184,93 @@ __device__ __forceinline__ void dif_pass(uint64_t *sh, int T, int logM, int rs, 
 // Whole transforms over the rows: radix-8 passes, then one radix-4 or radix-2
 // pass for the remaining bits. Each pass ends with a barrier.
 // Passes from sub-block size 2^logS0 down (logS0 < logM when the earlier passes
-// were done another way). With leave_r2, a final radix-2 pass is not run but left
-// to the caller's reader (r2_pair), and the return value says whether it was.
+// were done another way). With leave_tail, the last pass (radix 2, 4, or an untwiddled
+// radix 8, on sub-blocks of R consecutive words) is not run but left to the caller's
+// reader (tail_read), and its radix R is returned (0 when every pass ran).
 template <bool INV>
-__device__ __forceinline__ bool dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs,
-                                              const uint64_t *__restrict__ bfly, bool leave_r2 = false) {
+__device__ __forceinline__ int dif_rows_from(uint64_t *sh, int T, int logM, int logS0, int rs,
+                                             const uint64_t *__restrict__ bfly, bool leave_tail = false) {
   int logS = logS0;
   for (; logS >= 3; logS -= 3) {
     if (logS > 3) dif_pass<8, INV, true>(sh, T, logM, rs, logS, bfly);
+    else if (leave_tail) return 8;
     else dif_pass<8, INV, false>(sh, T, logM, rs, logS, bfly);
     __syncthreads();
   }
   if (logS == 2) {
+    if (leave_tail) return 4;
     dif_pass<4, INV, false>(sh, T, logM, rs, 2, bfly);
     __syncthreads();
   } else if (logS == 1) {
-    if (leave_r2) return true;
+    if (leave_tail) return 2;
     dif_pass<2, INV, false>(sh, T, logM, rs, 1, bfly);
     __syncthreads();
   }
-  return false;
+  return 0;
 }
 
 template <bool INV>
-__device__ __forceinline__ bool dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ bfly,
-                                         bool leave_r2 = false) {
-  return dif_rows_from<INV>(sh, T, logM, logM, rs, bfly, leave_r2);
+__device__ __forceinline__ int dif_rows(uint64_t *sh, int T, int logM, int rs, const uint64_t *__restrict__ bfly,
+                                        bool leave_tail = false) {
+  return dif_rows_from<INV>(sh, T, logM, logM, rs, bfly, leave_tail);
 }
 
-// The last radix-2 pass of a row transform (left by dif_rows_from) done by its reader:
-// for a frequency f < M/2 (M = 2^logM) the butterfly's inputs are at positions brev(f)
-// (even) and brev(f) + 1 of the row, and its outputs are frequencies f (x0) and
-// f + M/2 (x1). The pass has no twiddles in either direction.
-__device__ __forceinline__ void r2_pair(const uint64_t *row, int f, int logM, uint64_t &x0, uint64_t &x1) {
-  const int w = swz(brev(f, logM));  // swz(w + 1) = swz(w) ^ 1 for even w
-  const uint64_t a = row[w], b = row[w ^ 1];
-  x0 = gl::add(a, b);
-  x1 = gl::sub(a, b);
+// The last pass of a row transform (left by dif_rows_from) done by its reader: the R
+// words at positions p0 .. p0 + R - 1 of the row (p0 a multiple of R), transformed in
+// registers. Slot j then holds position p0 + j, i.e. for p0 = brev(f0) (f0 < M/R,
+// M = 2^logM) frequency f0 + brev_R(j) M/R. The pass has no twiddles in either direction.
+template <int R, bool INV>
+__device__ __forceinline__ void tail_read(const uint64_t *row, int p0, uint64_t v[R]) {
+  const int w = swz(p0);  // swz(p0 + j) = swz(p0) ^ j for j < 8 when R divides p0
+#pragma unroll
+  for (int j = 0; j < R; j++) v[j] = row[w ^ j];
+  reg_dif<R, INV>(v);
+}
+
+
+// Output loop of a pass whose row transforms left their last pass (radix R) to it. Group
+// g of the tile is (row t, first frequency f0 < M/R) = coords(g); its outputs are the
+// frequencies f0 + brev_R(j) M/R, each through val(t, f, v) (its twiddle or scale) and
+// put(t, f, v). Each thread takes OUT_BATCH/R groups per trip and forms every value
+// before the first store (groups past the end redo the last one and store nothing).
+template <int R, bool INV, class Coords, class Val, class Put>
+__device__ __forceinline__ void tail_out(const uint64_t *sh, int rs, int groups, int logM, Coords coords, Val val,
+                                         Put put) {
+  constexpr int G = OUT_BATCH / R, LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  for (int g0 = threadIdx.x; g0 < groups; g0 += G * LDE_THREADS) {
+    uint64_t r[G][R];
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      int t, f0;
+      coords(min(g0 + u * LDE_THREADS, groups - 1), t, f0);
+      uint64_t v[R];
+      tail_read<R, INV>(sh + t * rs, (int)brev(f0, logM), v);
+#pragma unroll
+      for (int j = 0; j < R; j++) r[u][j] = val(t, f0 + (brev_r<R>(j) << (logM - LR)), v[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int g = g0 + u * LDE_THREADS;
+      if (g < groups) {
+        int t, f0;
+        coords(g, t, f0);
+#pragma unroll
+        for (int j = 0; j < R; j++) put(t, f0 + (brev_r<R>(j) << (logM - LR)), r[u][j]);
+      }
+    }
+  }
+}
+
+// tail_out for the radix the row transforms left (2, 4 or 8; false when none was left).
+template <bool INV, class Coords, class Val, class Put>
+__device__ __forceinline__ bool tail_out_any(int R, const uint64_t *sh, int rs, int rows, int logM, Coords coords,
+                                             Val val, Put put) {
+  switch (R) {
+    case 2: tail_out<2, INV>(sh, rs, rows << (logM - 1), logM, coords, val, put); return true;
+    case 4: tail_out<4, INV>(sh, rs, rows << (logM - 2), logM, coords, val, put); return true;
+    case 8: tail_out<8, INV>(sh, rs, rows << (logM - 3), logM, coords, val, put); return true;
+    default: return false;
+  }
 }
 
 // One trace's LDE as the passes see it. Column c of the trace is trace + c*n,
@@ -255,7 +305,7 @@ __device__ __forceinline__ int lde_tiles3(const LdeTask &t) { return (1 << (t.L2
 template <bool INV, class Src>
 __device__ __forceinline__ void first_pass_global(uint64_t *sh, int T, int logT, int logM, int rs,
                                                   const uint64_t *__restrict__ bfly, Src src) {
-  const int logStride = logM - 3, stride = 1 << logStride;
+  const int logStride = logM - 3;
   const int nb = T << logStride;
   const uint64_t *rows = bfly + 8 * bfly_row0(logM);
   for (int b = threadIdx.x; b < nb; b += LDE_THREADS) {
@@ -286,19 +336,19 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
   uint64_t *y = s.y + size_t(col) * n;
   const int j2_0 = tile << s.logT1;
   const int total = T * n1;
-  bool r2;
+  int tail;
   if (s.L1 >= 4) {
     // the first radix-8 pass reads the trace straight from global memory
     first_pass_global<true>(sh, T, s.logT1, s.L1, rs, tw.bfly_inv,
                             [&](int t, int w) { return a[size_t(w) * n2 + j2_0 + t]; });
     __syncthreads();
-    r2 = dif_rows_from<true>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_inv, true);
+    tail = dif_rows_from<true>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_inv, true);
   } else {
     stage_tile(
         total, [&](int e) { return a[size_t(e >> s.logT1) * n2 + j2_0 + (e & (T - 1))]; },
         [&](int e, uint64_t v) { sh[(e & (T - 1)) * rs + swz(e >> s.logT1)] = v; });
     __syncthreads();
-    r2 = dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv, true);
+    tail = dif_rows<true>(sh, T, s.L1, rs, tw.bfly_inv, true);
   }
   const int shl = TW_LOG - s.L;
   constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
@@ -312,32 +362,12 @@ __device__ __forceinline__ void lde_pass1_tile(const LdeTask &s, const Twiddles 
     const uint64_t w = gl::mul(tw.inv_hi[x >> TW_HALF], tw.inv_lo[x & lo_mask]);
     return ex ? gl::mul(v, w) : v;
   };
-  if (r2) {
-    // the transforms' last radix-2 pass fused here: pair e gives k1 and k1 + n1/2
-    const int pairs = total >> 1;
-    for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
-      uint64_t r[OUT_BATCH];
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH / 2; u++) {
-        const int e = min(e0 + u * LDE_THREADS, pairs - 1);
-        const int t = e & (T - 1), k1 = e >> s.logT1;
-        uint64_t x0, x1;
-        r2_pair(sh + t * rs, k1, s.L1, x0, x1);
-        r[2 * u] = twiddled(t, k1, x0);
-        r[2 * u + 1] = twiddled(t, k1 + (n1 >> 1), x1);
-      }
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH / 2; u++) {
-        const int e = e0 + u * LDE_THREADS;
-        if (e < pairs) {
-          const int t = e & (T - 1), k1 = e >> s.logT1;
-          y[size_t(k1) * n2 + j2_0 + t] = r[2 * u];
-          y[size_t(k1 + (n1 >> 1)) * n2 + j2_0 + t] = r[2 * u + 1];
-        }
-      }
-    }
+  // the transforms' last pass done here: group g = (row t, first frequency k1 < n1/R)
+  if (tail_out_any<true>(
+          tail, sh, rs, T, s.L1,
+          [&](int g, int &t, int &k1) { t = g & (T - 1), k1 = g >> s.logT1; }, twiddled,
+          [&](int t, int k1, uint64_t v) { y[size_t(k1) * n2 + j2_0 + t] = v; }))
     return;
-  }
   for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
     uint64_t r[OUT_BATCH];
 #pragma unroll
@@ -400,32 +430,15 @@ __device__ __forceinline__ void lde_pass2i_tile(const LdeTask &s, const Twiddles
       total, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
       [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
   __syncthreads();
-  if (dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv, true)) {
-    // the transforms' last radix-2 pass fused here: pair e gives i and i + n2/2
-    const int pairs = total >> 1, lh = s.L2 - 1;
-    for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
-      uint64_t r[OUT_BATCH];
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH / 2; u++) {
-        const int e = min(e0 + u * LDE_THREADS, pairs - 1);
-        const int t = e >> lh, i = e & ((1 << lh) - 1);
-        uint64_t x0, x1;
-        r2_pair(sh + t * rs, i, s.L2, x0, x1);
-        const uint64_t sc = s.scale[k1_0 + t];
-        r[2 * u] = gl::mul(x0, sc);
-        r[2 * u + 1] = gl::mul(x1, sc);
-      }
-#pragma unroll
-      for (int u = 0; u < OUT_BATCH / 2; u++) {
-        const int e = e0 + u * LDE_THREADS;
-        if (e < pairs) {
-          uint64_t *row = y + size_t(k1_0 + (e >> lh)) * n2 + (e & ((1 << lh) - 1));
-          row[0] = r[2 * u];
-          row[n2 >> 1] = r[2 * u + 1];
-        }
-      }
-    }
-    return;
+  const int tail = dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv, true);
+  // the transforms' last pass done here: group g = (row t, first frequency i < n2/R)
+  {
+    const int lg = s.L2 - (tail == 8 ? 3 : tail == 4 ? 2 : 1);
+    if (tail_out_any<true>(
+            tail, sh, rs, T, s.L2, [&](int g, int &t, int &i) { t = g >> lg, i = g & ((1 << lg) - 1); },
+            [&](int t, int i, uint64_t v) { return gl::mul(v, s.scale[k1_0 + t]); },
+            [&](int t, int i, uint64_t v) { y[size_t(k1_0 + t) * n2 + i] = v; }))
+      return;
   }
   for (int e0 = threadIdx.x; e0 < total; e0 += OUT_BATCH * LDE_THREADS) {
     uint64_t r[OUT_BATCH];
@@ -497,7 +510,7 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
     default: twist_stage<16>(s, sh, rs, n_in, total_in, c); break;
   }
   __syncthreads();
-  const bool r2 = dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd, true);
+  const int tail = dif_rows_from<false>(sh, T, LW, s.L2, rs, tw.bfly_fwd, true);
   const int total_out = T << LW;
   const int shl = TW_LOG - logN;
   constexpr uint32_t lo_mask = (1u << TW_HALF) - 1;
@@ -516,32 +529,12 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
         return ex ? gl::mul(v, w) : v;
       }
     };
-    if (r2) {
-      // the transforms' last radix-2 pass fused here: pair e gives f and f + W/2
-      const int pairs = total_out >> 1, lh = LW - 1;
-      for (int e0 = threadIdx.x; e0 < pairs; e0 += (OUT_BATCH / 2) * LDE_THREADS) {
-        uint64_t r[OUT_BATCH];
-#pragma unroll
-        for (int u = 0; u < OUT_BATCH / 2; u++) {
-          const int e = min(e0 + u * LDE_THREADS, pairs - 1);
-          const int t = e >> lh, f = e & ((1 << lh) - 1);
-          uint64_t x0, x1;
-          r2_pair(sh + t * rs, f, LW, x0, x1);
-          r[2 * u] = twiddled(t, f, x0);
-          r[2 * u + 1] = twiddled(t, f + (W >> 1), x1);
-        }
-#pragma unroll
-        for (int u = 0; u < OUT_BATCH / 2; u++) {
-          const int e = e0 + u * LDE_THREADS;
-          if (e < pairs) {
-            uint64_t *row = zc + (size_t(k1_0 + (e >> lh)) << LW) + (e & ((1 << lh) - 1));
-            row[0] = r[2 * u];
-            row[W >> 1] = r[2 * u + 1];
-          }
-        }
-      }
+    // the transforms' last pass done here: group g = (row t, first frequency f < W/R)
+    const int lg = LW - (tail == 8 ? 3 : tail == 4 ? 2 : 1);
+    if (tail_out_any<false>(
+            tail, sh, rs, T, LW, [&](int g, int &t, int &f) { t = g >> lg, f = g & ((1 << lg) - 1); }, twiddled,
+            [&](int t, int f, uint64_t v) { zc[(size_t(k1_0 + t) << LW) + f] = v; }))
       return;
-    }
     for (int e0 = threadIdx.x; e0 < total_out; e0 += OUT_BATCH * LDE_THREADS) {
       uint64_t r[OUT_BATCH];
 #pragma unroll
@@ -612,13 +605,13 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
     else last_pass_global<2, false>(sh, T, s.logT3, s.L1, rs, dst);
     return;
   }
-  bool r2;
+  int tail;
   if (s.bitrev && s.L1 >= 4) {
     // the first radix-8 pass reads Z straight from global memory, as in natural layout
     first_pass_global<false>(sh, T, s.logT3, s.L1, rs, tw.bfly_fwd,
                              [&](int t, int w) { return zc[(size_t(w) << LW) + e0 + t]; });
     __syncthreads();
-    r2 = dif_rows_from<false>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_fwd, true);
+    tail = dif_rows_from<false>(sh, T, s.L1, s.L1 - 3, rs, tw.bfly_fwd, true);
   } else {
     stage_tile(
         total, [&](int e) { return zc[(size_t(e >> s.logT3) << LW) + e0 + (e & (T - 1))]; },
@@ -626,25 +619,30 @@ __device__ __forceinline__ void lde_pass3_tile(const LdeTask &s, const Twiddles 
     __syncthreads();
     // bit-reversed layout: the last radix-2 pass is left to the writer, which stores each
     // butterfly's two outputs (positions 2q and 2q + 1, adjacent in the output row) together
-    r2 = dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd, s.bitrev != 0);
+    tail = dif_rows<false>(sh, T, s.L1, rs, tw.bfly_fwd, s.bitrev != 0);
   }
   if (!s.bitrev) {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e & (T - 1), m2 = e >> s.logT3;
       out[size_t(e0 + t) + size_t(W) * m2] = sh[t * rs + swz(brev(m2, s.L1))];
     }
-  } else if (r2) {
-    const int lh = s.L1 - 1;
-    for (int e = threadIdx.x; e < (total >> 1); e += blockDim.x) {
-      const int t = e >> lh, q = e & ((1 << lh) - 1);
-      const uint64_t *row = sh + t * rs;
-      const int w = swz(2 * q);  // swz(2q + 1) = swz(2q) ^ 1
-      const uint64_t a = row[w], b = row[w ^ 1];
-      ulonglong2 v;
-      v.x = gl::add(a, b);
-      v.y = gl::sub(a, b);
-      *reinterpret_cast<ulonglong2 *>(out + size_t(brev(e0 + t, LW)) * n1 + 2 * q) = v;
-    }
+  } else if (tail) {
+    // the last pass done here: each group's R outputs are adjacent in the output row
+    auto put = [&](auto RT) {
+      constexpr int R = decltype(RT)::value, LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+      const int lg = s.L1 - LR;
+      for (int g = threadIdx.x; g < (total >> LR); g += blockDim.x) {
+        const int t = g >> lg, q = g & ((1 << lg) - 1);
+        uint64_t v[R];
+        tail_read<R, false>(sh + t * rs, q * R, v);
+        ulonglong2 *o = reinterpret_cast<ulonglong2 *>(out + size_t(brev(e0 + t, LW)) * n1 + q * R);
+#pragma unroll
+        for (int j = 0; j < R / 2; j++) o[j] = make_ulonglong2(v[2 * j], v[2 * j + 1]);
+      }
+    };
+    if (tail == 2) put(std::integral_constant<int, 2>{});
+    else if (tail == 4) put(std::integral_constant<int, 4>{});
+    else put(std::integral_constant<int, 8>{});
   } else {
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int t = e >> s.L1, p = e & (n1 - 1);
