@@ -47,8 +47,7 @@ __global__ void __launch_bounds__(THREADS) k_merkle_level(const uint64_t *__rest
 // The same two kernels with the matrix-core linear layer: each wave covers 64
 // consecutive rows (nodes), a block of THREADS threads covers THREADS of them. The
 // leaf kernel is held to 128 VGPRs (four waves per SIMD): left alone it takes 141 and
-// runs three, which measured slower than the one 8-byte value it then keeps in scratch
-// memory outside the loops.
+// runs three, which measured slower.
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_leaf_hash_mf(const uint64_t *__restrict__ mat, uint32_t n_cols,
                                                           uint64_t n_rows, uint64_t *__restrict__ dig,
                                                           const uint64_t *__restrict__ rc,

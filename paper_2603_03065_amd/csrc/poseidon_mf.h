@@ -216,11 +216,15 @@ __device__ __forceinline__ void leaf_digests_mf(const uint64_t *__restrict__ mat
   for (int u = 0; u < 2; u++)
 #pragma unroll
     for (int jj = 0; jj < 6; jj++) S[u][jj] = 0;
-  const uint64_t row = base + L.c;
-  const bool live0 = row < n_rows, live1 = row + 32 < n_rows;
-  const uint64_t *p = mat + uint64_t(6 * L.h) * n_rows + row;  // column 6h of row base + c
+  // the lane's row and column pointer are formed anew from the lane index in every chunk
+  // and for the store (the index hidden from the compiler, which would otherwise keep the
+  // 64-bit values live across the permutations and, at 128 VGPRs, spill them)
   for (uint32_t q = 0; q < n_cols; q += RATE) {
-    const uint64_t *pq = p + uint64_t(q) * n_rows;
+    uint32_t lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const uint64_t row = base + (lane & 31);
+    const bool live0 = row < n_rows, live1 = row + 32 < n_rows;
+    const uint64_t *pq = mat + uint64_t(6 * (lane >> 5) + q) * n_rows + row;  // column q + 6h
     if (L.h == 0) {
 #pragma unroll
       for (int jj = 0; jj < 6; jj++)
