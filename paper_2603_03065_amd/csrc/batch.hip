@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(lde::LDE_THREADS) __attribute__((amdgpu_waves_
   } else if (pass == 2) {
     const int tiles = lde::lde_tiles2(t);
     const int col = local / tiles;
-    lde::lde_pass2_tile<true>(t, tw, sh, col, col, local % tiles);
+    lde::lde_pass2_tile(t, tw, sh, col, col, local % tiles);
   } else {
     const int tiles = lde::lde_tiles3(t);
     const int col = local / tiles;

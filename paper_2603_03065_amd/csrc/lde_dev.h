@@ -413,7 +413,6 @@ __device__ __forceinline__ void twist_stage(const LdeTask &s, uint64_t *sh, int 
   }
 }
 
-// Pass 2, tile = T consecutive residues k1 (rows of Y) of column col; W = B*n2.
 // Pass 2's inverse part on its own, tile = T2i consecutive rows k1 of Y (column col):
 // row k1 is transformed back, giving n*c[k1 + n1*k2] in bit-reversed positions, and
 // written over itself in natural order k2, times n^-1 s^k1. A tile holds up to 8192
@@ -457,14 +456,12 @@ __device__ __forceinline__ void lde_pass2i_tile(const LdeTask &s, const Twiddles
 }
 
 // Pass 2, tile = T consecutive residues k1 (rows of Y) of column col; W = B*n2.
-// Row k1 of Y is transformed back (giving n*c[k1 + n1*k2] in bit-reversed
-// positions), scaled by n^-1 s^k1 and expanded to the W-point zero-padded
-// transform: its first radix-B decimation-in-frequency pass has a single
-// nonzero input per butterfly, so output slot j of butterfly i is the input
-// times the twist (s^n1 w_W^r)^i, r = bitrev(j). The remaining passes run on the
-// B cosets together; row k1 of Z gets Z[k1][e] = w_N^(k1 e) * (result at e).
-// PRE: the rows of Y already hold n^-1 s^k1 c' in natural order (lde_pass2i_tile).
-template <bool PRE>
+// Row k1 of Y holds n^-1 s^k1 c' in natural order (written by lde_pass2i_tile); it is
+// expanded to the W-point zero-padded transform: its first radix-B
+// decimation-in-frequency pass has a single nonzero input per butterfly, so output
+// slot j of butterfly i is the input times the twist (s^n1 w_W^r)^i, r = bitrev(j).
+// The remaining passes run on the B cosets together; row k1 of Z gets
+// Z[k1][e] = w_N^(k1 e) * (result at e).
 __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles &tw, uint64_t *sh, int col, int zcol,
                                                int tile) {
   const int n2 = 1 << s.L2, T = 1 << s.logT2;
@@ -478,29 +475,12 @@ __device__ __forceinline__ void lde_pass2_tile(const LdeTask &s, const Twiddles 
   // this thread's inputs m < n_in (the same count for the whole block): n^-1 s^k1 c'
   const int n_in = (total_in + LDE_THREADS - 1) / LDE_THREADS;
   uint64_t c[MAX_PER_THREAD];
-  if (PRE) {
 #pragma unroll
-    for (int m = 0; m < MAX_PER_THREAD; m++) {
-      if (m < n_in) {
-        const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
-        c[m] = y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))];
-      }
+  for (int m = 0; m < MAX_PER_THREAD; m++) {
+    if (m < n_in) {
+      const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
+      c[m] = y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))];
     }
-  } else {
-    stage_tile(
-        total_in, [&](int e) { return y[size_t(k1_0 + (e >> s.L2)) * n2 + (e & (n2 - 1))]; },
-        [&](int e, uint64_t v) { sh[(e >> s.L2) * rs + swz(e & (n2 - 1))] = v; });
-    __syncthreads();
-    dif_rows<true>(sh, T, s.L2, rs, tw.bfly_inv);
-#pragma unroll
-    for (int m = 0; m < MAX_PER_THREAD; m++) {
-      if (m < n_in) {
-        const int e = min(threadIdx.x + m * LDE_THREADS, total_in - 1);
-        const int t = e >> s.L2, i = e & (n2 - 1);
-        c[m] = gl::mul(sh[t * rs + swz(brev(i, s.L2))], s.scale[k1_0 + t]);
-      }
-    }
-    __syncthreads();
   }
   switch (s.b) {
     case 0: twist_stage<1>(s, sh, rs, n_in, total_in, c); break;

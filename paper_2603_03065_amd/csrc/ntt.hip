@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_e
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass2(LdeTask s, Twiddles tw, int col0) {
   extern __shared__ uint64_t sh[];
   const int col = col0 + blockIdx.y;
-  lde_pass2_tile<true>(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
+  lde_pass2_tile(s, tw, sh, col, s.bitrev ? (int)blockIdx.y : col, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(LDE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_lde_pass3(LdeTask s, Twiddles tw, int col0) {
