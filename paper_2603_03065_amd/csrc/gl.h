@@ -258,9 +258,21 @@ GL_HD uint64_t sub(uint64_t a, uint64_t b) {  // a, b canonical
 
 // relaxed a + canonical b -> relaxed
 GL_HD uint64_t add_r(uint64_t a, uint64_t b) {
+#ifdef __HIP_DEVICE_COMPILE__
+  // the sum on the carry chain, then + c * (2^32 - 1) for its carry c out of bit 64 as
+  // a subtract-with-borrow on the low word and an add-with-carry on the high word; with
+  // a carry the sum is a + b - 2^64 < p - 1, whose high word is at most 2^32 - 2
+  uint64_t c1, c, bb;
+  const uint32_t s0 = isa::add_co((uint32_t)a, (uint32_t)b, c1);
+  const uint32_t s1 = isa::addc((uint32_t)(a >> 32), (uint32_t)(b >> 32), c1, c);
+  const uint32_t r0 = isa::subb0(s0, c, bb);
+  const uint32_t r1 = isa::addc0(s1, c & ~bb);
+  return ((uint64_t)r1 << 32) | r0;
+#else
   uint64_t s = a + b;
   if (s < b) s += EPS;               // a + b - 2^64 < p - 1, so no second carry
   return s;
+#endif
 }
 
 GL_HD uint64_t pow(uint64_t a, uint64_t e) {

@@ -16,7 +16,7 @@
 //   * B column = one permutation; a lane supplies the K slots of its half
 //     (16h .. 16h+15), slot 4q + 2w + l holding b'_jk, k = 2p + l, of its word
 //     jj = 2q + w, with b' = b - 128 (the byte XOR 0x80 read as signed); slots 12..15
-//     are unused (zero in A);
+//     are unused (zero in A, so whatever their register holds adds nothing);
 //   * a circulant entry C may reach 254, beyond int8, so it is split between two
 //     matrices, A1 holding ceil(C/2) and A2 floor(C/2), and the matrix core adds the two
 //     products (the second takes the first's result as its addend); every entry must
@@ -88,7 +88,9 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
 #pragma unroll
     for (int jj = 0; jj < 6; jj++) S[u][jj] = gl::add_r(S[u][jj], rc[6 * h + jj]);
 #pragma unroll 1
-  for (int r = 0; r < ROUNDS; r++) {
+  for (int r0 = 0; r0 < ROUNDS; r0++) {
+    // the round number as a scalar: the round test and the table row stay off the VALU
+    const int r = __builtin_amdgcn_readfirstlane(r0);
     const bool full = r < FULL_HALF || r >= ROUNDS - FULL_HALF;
     if (full) {
 #pragma unroll
@@ -103,7 +105,7 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
       S[0][0] = sbox(S[0][0]);
       mf_swap(S[0][0], S[1][0]);
     }
-    const uint64_t *kr = tab + MF_RCK + (size_t(r + 1) * WIDTH + 6 * h) * 2;
+    const uint64_t *kr = tab + MF_RCK + size_t(r + 1) * WIDTH * 2 + 12u * (uint32_t)h;
     uint32_t dw[2][6][2];
 #pragma unroll
     for (int u = 0; u < 2; u++)
@@ -130,7 +132,11 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
         B[u][0] = (int)__builtin_amdgcn_perm(dw[u][1][half], dw[u][0][half], sel);
         B[u][1] = (int)__builtin_amdgcn_perm(dw[u][3][half], dw[u][2][half], sel);
         B[u][2] = (int)__builtin_amdgcn_perm(dw[u][5][half], dw[u][4][half], sel);
-        B[u][3] = 0;  // K slots 12..15: zero entries in A
+        // K slots 12..15 meet zero entries of A: the register is left as it is (an empty
+        // asm statement defines it), which saves a move per operand
+        int pad;
+        asm volatile("" : "=v"(pad));
+        B[u][3] = pad;
       }
       mf_v16i D[2];
 #pragma unroll
