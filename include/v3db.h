@@ -102,10 +102,10 @@ v3db_status v3db_poseidon_constants(const v3db_ctx *ctx, uint64_t *rc_out, uint6
  * than 2^15 nodes, batch phases, snapshot records) use for the permutation's
  * linear layer (the circulant product of the hash fixed above); both give
  * identical results, the arithmetic being exact.
- *   1  int8 matrix cores: every circulant entry is at most 254, so each splits
- *      into two signed bytes (the default seed's entries are all below 230);
- *   0  VALU multiply-adds: an entry equals 255, or the environment variable
- *      V3DB_POSEIDON_VALU was set to a non-zero value when the context was made;
+ *   1  int8 matrix cores (the default: each circulant entry C, 1..255, is held
+ *      as the signed byte C - 128);
+ *   0  VALU multiply-adds: the environment variable V3DB_POSEIDON_VALU was set
+ *      to a non-zero value when the context was made;
  *  -1  ctx is NULL.
  * The single-permutation call, openings, tree tops and the FRI fold are the same
  * either way. */

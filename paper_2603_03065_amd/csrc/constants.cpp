@@ -109,42 +109,54 @@ bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts) {
   return false;
 }
 
-// Matrix-core linear layer (poseidon_mf.h): two int8 matrices A1, A2 (32 x 32) whose
-// products add to the circulant applied to two byte limbs l = 0, 1 at once. Row of
-// output i = 6h + ii (h = i / 6), limb l: 8 (e / 4) + 4h + e % 4 with e = 6l + ii, where
-// the 32x32 output layout puts it in the lanes that hold words 6h .. 6h+5. Column of
-// word j = 6h' + 2q + w, limb l: 16h' + 4q + 2w + l, holding ceil(C/2) (A1) or floor(C/2)
-// (A2) of C = a[(j - i) mod 12] in the rows of limb l, zero in those of the other limb.
-// Lane x holds row x % 32, columns 16 (x / 32) .. +15 as 16 bytes of each matrix. The
-// accumulator start values are K + (next round constant).lo and K + (next round
-// constant).hi with K = 128 (sum_j a_j) (2^24 + 2^16 + 2^8 + 1), which offsets the
-// bytes' -128 shift.
+// Matrix-core linear layer (poseidon_mf.h): one int8 matrix A (32 x 32) holding C - 128
+// for each circulant entry C = a[(j - i) mod 12], applied to two byte limbs l = 0, 1 at
+// once. Row of output i = 6h + ii (h = i / 6), limb l: 8 (e / 4) + 4h + e % 4 with
+// e = 6l + ii, where the 32x32 output layout puts it in the lanes that hold words
+// 6h .. 6h+5. Column of word j = 6h' + 2q + w, limb l: 16h' + 4q + 2w + l; the row of
+// output i, limb l holds C - 128 in the columns of limb l, zero in those of the other
+// limb. Rows for e = 12, 13 (24 + 4h and 25 + 4h, both halves h) hold -128 in every
+// column of limb 0, resp. 1: minus 128 times the byte sum, which the kernel adds back
+// to every output (with the weights -1 and -2^16 kept as the table's second and fourth
+// limb weights). Columns 12..15 and 28..31 stay zero. Lane x holds row x % 32, columns
+// 16 (x / 32) .. +15 as 16 bytes. The accumulator start values are
+// K + (next round constant).lo and K + (next round constant).hi with
+// K = 128 (sum_j a_j) (2^24 + 2^16 + 2^8 + 1).
 bool build_mf_table(const PoseidonTables &t, uint64_t out[MF_TABLE_WORDS]) {
   memset(out, 0, MF_TABLE_WORDS * sizeof(uint64_t));
   uint64_t R = 0;
   for (int j = 0; j < WIDTH; j++) {
-    if (t.circ[j] > 254) return false;
+    if (t.circ[j] > 255) return false;
     R += t.circ[j];
   }
-  int8_t A[2][32][32] = {};
+  int8_t A[32][32] = {};
+  for (int h = 0; h < 2; h++)
+    for (int l = 0; l < 2; l++) {
+      const int e = 12 + l, row = 8 * (e / 4) + 4 * h + e % 4;
+      for (int j = 0; j < WIDTH; j++) {
+        const int jj = j % 6;
+        A[row][16 * (j / 6) + 4 * (jj / 2) + 2 * (jj % 2) + l] = -128;
+      }
+    }
   for (int i = 0; i < WIDTH; i++) {
     const int h = i / 6, ii = i % 6;
     for (int l = 0; l < 2; l++) {
       const int e = 6 * l + ii, row = 8 * (e / 4) + 4 * h + e % 4;
       for (int j = 0; j < WIDTH; j++) {
-        const uint32_t C = t.circ[(j - i + WIDTH) % WIDTH];
+        const int C = (int)t.circ[(j - i + WIDTH) % WIDTH];
         const int jj = j % 6, col = 16 * (j / 6) + 4 * (jj / 2) + 2 * (jj % 2) + l;
-        A[0][row][col] = (int8_t)((C + 1) / 2);
-        A[1][row][col] = (int8_t)(C / 2);
+        A[row][col] = (int8_t)(C - 128);
       }
     }
   }
   uint8_t *am = reinterpret_cast<uint8_t *>(out + MF_AMAT);
-  for (int m = 0; m < 2; m++)
-    for (int x = 0; x < 64; x++)
-      for (int b = 0; b < 16; b++) am[m * 1024 + x * 16 + b] = (uint8_t)A[m][x % 32][16 * (x / 32) + b];
+  for (int x = 0; x < 64; x++)
+    for (int b = 0; b < 16; b++) am[x * 16 + b] = (uint8_t)A[x % 32][16 * (x / 32) + b];
   int32_t *mult = reinterpret_cast<int32_t *>(out + MF_MULT);
-  for (int k = 0; k < 4; k++) mult[k] = 1 << (8 * k);
+  mult[0] = 1;
+  mult[1] = -1;
+  mult[2] = 1 << 16;
+  mult[3] = -(1 << 16);
   const uint64_t K = 128 * R * 0x01010101ull;
   for (int r = 0; r <= ROUNDS; r++)
     for (int i = 0; i < WIDTH; i++) {

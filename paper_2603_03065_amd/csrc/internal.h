@@ -22,11 +22,10 @@ constexpr uint64_t MERKLE_WIDE_MAX_NODES = uint64_t(1) << 15;
 // ... and levels of at most this many, latency-bound, 32 lanes per node.
 constexpr uint64_t MERKLE_PAIR_MAX_NODES = uint64_t(1) << 11;
 constexpr size_t POS_TABLE_WORDS = (ROUNDS + 1) * WIDTH + WIDTH * WIDTH / 2;
-// Table of the matrix-core linear layer (poseidon_mf.h), in 64-bit words: the two
-// int8 half matrices A1, A2, each as 16 bytes per lane, the four limb weights as int32,
-// then (ROUNDS + 1) x WIDTH pairs {lo, hi} of accumulator start values (row r + 1 used
-// by round r).
-constexpr size_t MF_AMAT = 0, MF_MULT = 256, MF_RCK = 258;
+// Table of the matrix-core linear layer (poseidon_mf.h), in 64-bit words: the int8
+// matrix as 16 bytes per lane, the four limb weights as int32, then (ROUNDS + 1) x WIDTH
+// pairs {lo, hi} of accumulator start values (row r + 1 used by round r).
+constexpr size_t MF_AMAT = 0, MF_MULT = 128, MF_RCK = 130;
 constexpr size_t MF_TABLE_WORDS = MF_RCK + size_t(ROUNDS + 1) * WIDTH * 2;
 constexpr int TW_LOG = 26;        // largest transform, 2^26 points
 constexpr int TW_HALF = 13;       // two-level twiddle table: 2^13 x 2^13
@@ -137,8 +136,8 @@ v3db_status ctx_scratch(v3db_ctx *ctx, hipStream_t stream, size_t bytes, void **
 uint64_t splitmix64(uint64_t seed, uint64_t i);
 bool derive_poseidon(uint64_t seed, PoseidonTables &out, uint32_t &attempts);
 bool circulant_is_mds(const uint32_t circ[WIDTH]);
-// The matrix-core linear layer's table; false if an entry exceeds 254 (it would not
-// split into two int8 halves), in which case the hash kernels keep the VALU form.
+// The matrix-core linear layer's table; false if an entry exceeds 255 (C - 128 would
+// not fit a signed byte), in which case the hash kernels keep the VALU form.
 bool build_mf_table(const PoseidonTables &t, uint64_t out[MF_TABLE_WORDS]);
 
 // Tables (ntt.hip).

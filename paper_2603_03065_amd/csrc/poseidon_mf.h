@@ -11,32 +11,32 @@
 // The linear layer y_i = sum_j a[(j-i) mod 12] s_j is exact over the integers
 // before the reduction, and it is computed limb by limb: with b_jk byte k of s_j,
 //   y_i = sum_k 2^(8k) sum_j C_ij b_jk.
-// v_mfma_i32_32x32x32_i8 (signed bytes, int32 sums) forms sum_j C_ij b_jk for two
-// limbs k = 2p, 2p + 1 of the 32 permutations of one half of the wave:
+// v_mfma_i32_32x32x32_i8 (signed bytes, int32 sums) works on two limbs k = 2p, 2p + 1
+// of the 32 permutations of one half of the wave:
 //   * B column = one permutation; a lane supplies the K slots of its half
 //     (16h .. 16h+15), slot 4q + 2w + l holding b'_jk, k = 2p + l, of its word
 //     jj = 2q + w, with b' = b - 128 (the byte XOR 0x80 read as signed); slots 12..15
 //     are unused (zero in A, so whatever their register holds adds nothing);
-//   * a circulant entry C may reach 254, beyond int8, so it is split between two
-//     matrices, A1 holding ceil(C/2) and A2 floor(C/2), and the matrix core adds the two
-//     products (the second takes the first's result as its addend); every entry must
-//     be at most 254 (the host checks and otherwise keeps the VALU form);
-//   * the A row of output i and limb l holds the half entries of words j in the slots
-//     of limb l, zero in those of the other limb;
+//   * both factors shifted by 128 fit a signed byte (C - 128 for an entry C <= 255):
+//     (C - 128)(b - 128) = C b - 128 b' - 128 C, so with the A row of output i
+//     and limb l holding C_ij - 128 in the slots of limb l (zero in those of the other),
+//       D_ik = sum_j C_ij b_jk - 128 S_k - 128 R,  S_k = sum_j b'_jk, R = sum_j C_ij
+//     (R the same for every row of a circulant); two more rows of A, -128 in all the
+//     slots of limb 0 resp. 1, give -128 S_k in the same product;
 //   * D row 8(e/4) + 4h + e%4 of column c lands in lane 32h + c, element e: the
-//     host puts output i = 6h + ii, limb l in the row of element e = 6l + ii, so each
-//     lane receives exactly the outputs for the words it holds, both limbs.
-// One v_perm then packs two limbs of two words, and a round takes 24 of them for
-// eight limbs of twelve words (one limb per product took 48).
-// With b' = b - 128, sum_k 2^(8k) D_ik = y_i - 128 R G, R = sum_j C_ij (the same
-// for every row of a circulant) and G = sum_k 2^(8k). Each output accumulates
-// lo = K + rc.lo + sum_{k<4} 2^(8k) D_ik and hi = K + rc.hi + sum_{k>=4} ...,
-// K = 128 R (2^24 + 2^16 + 2^8 + 1) making both non-negative (D_ik >= -128 R) and
-// below 2^46, then fold(lo, hi) gives the relaxed output exactly as in the VALU
-// form. The start values K + next round's constant come from a small table. A limb
-// pair's two sums are first joined in 32 bits (|D| < 2^19), then added with one 64-bit
-// multiply-add: as many instructions as one multiply-add per limb, but half the 64-bit
-// products, which measured faster (the hash kernels run at the card's power limit).
+//     host puts output i = 6h + ii, limb l in the row of element e = 6l + ii, and
+//     -128 S of limbs 0 and 1 in the rows of elements 12 and 13 of both halves, so each
+//     lane receives exactly the outputs for the words it holds, both limbs, and S.
+// One v_perm packs two limbs of two words, and a round takes 24 of them for eight limbs
+// of twelve words, and 8 matrix products (one per limb pair and half of the wave).
+// Each output accumulates lo = K + rc.lo + sum_{k<4} 2^(8k) (D_ik + 128 S_k) and hi
+// likewise over k >= 4, K = 128 R (2^24 + 2^16 + 2^8 + 1): a limb pair's two sums are
+// first joined in 32 bits (|D| < 2^18), then added with one 64-bit multiply-add; the
+// 128 S terms, the same for all outputs of a permutation, are summed the same way once
+// (with negated weights) and added to each output's lo and hi. Both are then exact,
+// non-negative and below
+// 2^46, and fold(lo, hi) gives the relaxed output exactly as in the VALU form. The
+// start values K + next round's constant come from a small table.
 #pragma once
 #include "poseidon_dev.h"
 
@@ -47,8 +47,8 @@ typedef int mf_v4i __attribute__((ext_vector_type(4)));
 typedef int mf_v16i __attribute__((ext_vector_type(16)));
 
 struct MfLane {
-  mf_v4i A1, A2;  // this lane's 16 bytes of each half matrix
-  int mult[4];  // 1, 2^8, 2^16, 2^24 read from the table: each term stays one v_mad_i64_i32
+  mf_v4i A;  // this lane's 16 bytes of the matrix
+  int mult[4];  // 1, -1, 2^16, -2^16 read from the table: each term stays one v_mad_i64_i32
   int h, c;
 };
 
@@ -59,10 +59,7 @@ __device__ __forceinline__ MfLane mf_lane(const uint64_t *__restrict__ tab) {
   L.c = l & 31;
   const uint32_t *am = reinterpret_cast<const uint32_t *>(tab + MF_AMAT) + l * 4;
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    L.A1[q] = (int)am[q];
-    L.A2[q] = (int)am[64 * 4 + q];
-  }
+  for (int q = 0; q < 4; q++) L.A[q] = (int)am[q];
   const int *m = reinterpret_cast<const int *>(tab + MF_MULT);
 #pragma unroll
   for (int q = 0; q < 4; q++) L.mult[q] = m[q];
@@ -114,7 +111,7 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
         dw[u][jj][0] = (uint32_t)S[u][jj] ^ 0x80808080u;
         dw[u][jj][1] = (uint32_t)(S[u][jj] >> 32) ^ 0x80808080u;
       }
-    int64_t lo[2][6], hi[2][6];
+    int64_t lo[2][6], hi[2][6], sum[2];
 #pragma unroll
     for (int ii = 0; ii < 6; ii++) {
       lo[0][ii] = lo[1][ii] = (int64_t)kr[2 * ii];
@@ -140,16 +137,14 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
       }
       mf_v16i D[2];
 #pragma unroll
-      for (int u = 0; u < 2; u++) D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A1, B[u], (mf_v16i){}, 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < 2; u++) D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A2, B[u], D[u], 0, 0, 0);
-      // all four products issued before any is read: the matrix core runs the later
-      // ones while the earlier results are recombined
+      for (int u = 0; u < 2; u++) D[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(L.A, B[u], (mf_v16i){}, 0, 0, 0);
+      // both products issued before either is read: the matrix core runs the second
+      // while the first is recombined
       __builtin_amdgcn_sched_barrier(0);
-      // the two limbs first added in 32 bits (|D| < 2^19, so D_2p + 2^8 D_2p+1 fits),
+      // the two limbs first added in 32 bits (|D| < 2^18, so D_2p + 2^8 D_2p+1 fits),
       // then one 64-bit multiply-add per word and limb pair
 #pragma unroll
-      for (int u = 0; u < 2; u++)
+      for (int u = 0; u < 2; u++) {
 #pragma unroll
         for (int ii = 0; ii < 6; ii++) {
           const int32_t pr = (int32_t)(((uint32_t)D[u][6 + ii] << 8) + (uint32_t)D[u][ii]);
@@ -157,6 +152,22 @@ __device__ __forceinline__ void permute_mf(uint64_t S[2][6], const MfLane &L, co
           if (p < 2) lo[u][ii] += t;
           else hi[u][ii] += t;
         }
+        // -128 S of the pair (|128 S| < 2^18), weighted by minus the pair's weight
+        const int32_t ps = (int32_t)(((uint32_t)D[u][13] << 8) + (uint32_t)D[u][12]);
+        const int64_t t = (int64_t)ps * (int64_t)L.mult[((2 * p) & 3) + 1];
+        sum[u] = (p & 1) ? sum[u] + t : t;
+      }
+      // 128 times the byte sums of limbs 0..3 (after p = 1) or 4..7 (after p = 3),
+      // added to every output's lo or hi
+      if (p & 1) {
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+#pragma unroll
+          for (int ii = 0; ii < 6; ii++) {
+            if (p < 2) lo[u][ii] += sum[u];
+            else hi[u][ii] += sum[u];
+          }
+      }
     }
 #pragma unroll
     for (int u = 0; u < 2; u++)

@@ -1,10 +1,11 @@
 """GPU: the two forms of the permutation's linear layer in the bulk hashing
-kernels, int8 matrix cores (every circulant entry at most 254, the default seed
-included) and VALU multiply-adds (a circulant with an entry of 255, or
-V3DB_POSEIDON_VALU=1), each equal to the oracle and to each other word for word:
-leaf rows with ragged column counts, tree levels wide enough for the
-one-node-per-lane kernels, batch phases with traces of fewer rows than a wave,
-snapshot records and FRI trees."""
+kernels, int8 matrix cores (the default; entries shifted by -128, so every entry
+up to 255 fits a signed byte) and VALU multiply-adds (V3DB_POSEIDON_VALU=1), each
+equal to the oracle and to each other word for word: leaf rows with ragged column
+counts, tree levels wide enough for the one-node-per-lane kernels, batch phases
+with traces of fewer rows than a wave, snapshot records and FRI trees; and a
+circulant with an entry of 255 (the shifted entry 127, the int8 maximum) on the
+matrix cores."""
 import numpy as np
 import pytest
 
@@ -96,7 +97,7 @@ def test_path_selection(v3db, monkeypatch):
     with v3db.Context(0) as c:
         assert c.hash_path == "mfma"
     with v3db.Context(0, seed=SEED_255) as c:
-        assert c.hash_path == "valu"
+        assert c.hash_path == "mfma"
     monkeypatch.setenv("V3DB_POSEIDON_VALU", "1")
     with v3db.Context(0) as c:
         assert c.hash_path == "valu"
@@ -124,10 +125,10 @@ def test_matrix_cores_and_valu_agree_with_oracle(v3db, poseidon, oracle_mod, mon
     _check_against_oracle(got_mf, ins, poseidon)
 
 
-def test_circulant_with_255_falls_back_and_matches_oracle(v3db, oracle_mod):
+def test_circulant_with_255_on_matrix_cores_matches_oracle(v3db, oracle_mod):
     oracle_mod.set_threads(0)
     pos = oracle_mod.Poseidon(SEED_255)
     with v3db.Context(0, seed=SEED_255) as c:
-        assert c.hash_path == "valu"
+        assert c.hash_path == "mfma"
         got, ins = _run_all(v3db, c)
     _check_against_oracle(got, ins, pos)

@@ -1,14 +1,15 @@
-"""The seeds the two linear-layer forms are tested with: the default seed's
-circulant has every entry at most 254 (each splits into two signed bytes, so the
-bulk hashing kernels use the int8 matrix cores), and seed 53's has an entry of
-255 (so they keep the VALU form). Constants from the oracle's own derivation."""
+"""The seeds the matrix-core linear layer is tested with: it holds each circulant
+entry C as the signed byte C - 128 (so every entry 1..255 fits) and gives the
+byte sums of each limb from two all-ones rows. The default seed's entries lie
+well inside that range; seed 53's circulant has the largest entry, 255 (C - 128 =
+127, the signed-byte maximum). Constants from the oracle's own derivation."""
 
 
-def test_default_seed_entries_split_into_two_signed_bytes(poseidon):
+def test_default_seed_entries_fit_a_signed_byte_after_the_shift(poseidon):
     circ = [int(a) for a in poseidon.circ]
-    assert max(circ) <= 254 and all((a + 1) // 2 <= 127 and a // 2 <= 127 and (a + 1) // 2 + a // 2 == a
-                                     for a in circ)
+    assert all(-128 <= a - 128 <= 127 for a in circ) and max(circ) < 255
 
 
 def test_seed_53_has_an_entry_of_255(oracle_mod):
-    assert 255 in [int(a) for a in oracle_mod.Poseidon(53).circ]
+    circ = [int(a) for a in oracle_mod.Poseidon(53).circ]
+    assert 255 in circ and max(a - 128 for a in circ) == 127
