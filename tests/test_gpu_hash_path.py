@@ -3,8 +3,8 @@ kernels, int8 matrix cores (the default; entries shifted by -128, so every entry
 up to 255 fits a signed byte) and VALU multiply-adds (V3DB_POSEIDON_VALU=1), each
 equal to the oracle and to each other word for word: leaf rows with ragged column
 counts, tree levels wide enough for the one-node-per-lane kernels, batch phases
-with traces of fewer rows than a wave, snapshot records and FRI trees; and a
-circulant with an entry of 255 (the shifted entry 127, the int8 maximum) on the
+with traces of fewer rows than a wave, snapshot records and FRI trees; and
+circulants with the extreme entries 255 and 1 (held as 127 and -127) on the
 matrix cores."""
 import numpy as np
 import pytest
@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 P = inputs.P
 DEFAULT_SEED = 260303065
 SEED_255 = 53  # its circulant (found by search over seeds) has 255 as its last entry
+SEED_1_255 = 293  # its circulant has both extremes, 1 and 255 (held as -127 and 127)
 
 
 @pytest.fixture(scope="module")
@@ -125,10 +126,11 @@ def test_matrix_cores_and_valu_agree_with_oracle(v3db, poseidon, oracle_mod, mon
     _check_against_oracle(got_mf, ins, poseidon)
 
 
-def test_circulant_with_255_on_matrix_cores_matches_oracle(v3db, oracle_mod):
+@pytest.mark.parametrize("seed", [SEED_255, SEED_1_255])
+def test_circulant_extremes_on_matrix_cores_match_oracle(v3db, oracle_mod, seed):
     oracle_mod.set_threads(0)
-    pos = oracle_mod.Poseidon(SEED_255)
-    with v3db.Context(0, seed=SEED_255) as c:
+    pos = oracle_mod.Poseidon(seed)
+    with v3db.Context(0, seed=seed) as c:
         assert c.hash_path == "mfma"
         got, ins = _run_all(v3db, c)
     _check_against_oracle(got, ins, pos)
